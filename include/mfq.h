@@ -1,0 +1,164 @@
+/*
+ * mfq.h -- monitored free-fermion quantum trajectories on AMD MI355X (gfx950).
+ *
+ * C ABI of the library libmfq.so.  It implements the quantum-trajectory method
+ * of arXiv:2508.18468 (Fan, Yin, Garcia-Garcia, "Entanglement dynamics of
+ * monitored noninteracting fermions on graphics processing units") for
+ * noninteracting U(1) fermions with nearest-neighbour hopping:
+ *
+ *   state     Slater determinant of N orbitals: an L x N complex matrix U with
+ *             U^+ U = 1, correlation matrix C = U U^+      (Appendix A, Eq. (A3))
+ *   step      U <- exp(-i Ht dt) U, then either projective measurements of n_i
+ *             (Eq. (A1), Eq. (A2) with the sign of its rank-1 term corrected)
+ *             or the homodyne factor of Eq. (A4); then re-orthonormalisation
+ *             (Appendix A, QR after each step; done here by Cholesky-QR2)
+ *   observe   S_A from the eigenvalues of C restricted to A (Sec. II entropy
+ *             formula), mutual information I2 = S_A + S_B - S_AuB (Sec. IV)
+ *
+ * Conventions shared by every call:
+ *   - Complex numbers are interleaved (re, im) IEEE doubles (16 bytes).
+ *   - U of trajectory t is column-major L x N with leading dimension L; the
+ *     n_traj trajectories are stored one after another (stride L*N), so the
+ *     whole batch is one column-major L x (N*n_traj) matrix.
+ *   - Sites are numbered i = x + Lx*y (y = 0 in 1d).  Regions are lists of
+ *     distinct site ids in [0, L), strictly ascending; otherwise MFQ_EINVAL.
+ *   - All device work is ordered on the context's HIP stream.  mfq_step is
+ *     asynchronous; calls that return host data synchronise the stream.
+ *   - Random numbers: Philox4x64-10, key = (seed, uid of the trajectory),
+ *     counter = (absolute step index n >= 1, site i, purpose, 0); purpose 0
+ *     = projective (word 0 selects the site, word 1 decides the outcome),
+ *     purpose 1 = homodyne (words 0 and 1 give one Box-Muller normal).  The
+ *     draws of a trajectory depend only on (seed, uid, n, i): one call of n
+ *     steps equals n calls of one step, and batching never changes results.
+ *   - Every call returns MFQ_OK (0) or a negative error code; none aborts and
+ *     none throws.  mfq_last_error() describes the last failure on a context.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef MFQ_H
+#define MFQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfq_ctx mfq_ctx;
+typedef int32_t mfq_status;
+
+#define MFQ_OK 0
+#define MFQ_EINVAL (-1)   /* bad argument (null pointer, size, region, order) */
+#define MFQ_ENOMEM (-2)   /* device allocation failed or workspace too small */
+#define MFQ_EDEVICE (-3)  /* HIP runtime error */
+#define MFQ_ENUMERIC (-4) /* Cholesky breakdown or a non-finite value */
+#define MFQ_ESTATE (-5)   /* call out of order (e.g. step before init_state) */
+
+#define MFQ_PROJECTIVE 0  /* projective n_i measurements, Appendix A (PM) */
+#define MFQ_HOMODYNE 1    /* homodyne / quantum state diffusion, Eq. (A4) (QSD) */
+
+#define MFQ_FP64 0        /* every step in FP64 */
+
+/* Lattice of Sec. II (1d ring) or Sec. IV (2d torus); periodic boundaries,
+ * nearest-neighbour hopping Ht_ij = J.  dim = 1: L = Lx (Ly ignored);
+ * dim = 2: L = Lx*Ly.  Lx (and Ly for dim 2) must be >= 2. */
+typedef struct {
+  int32_t dim;
+  int32_t Lx;
+  int32_t Ly;
+  int32_t reserved;
+  double J;
+} mfq_lattice;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * order all work on, or NULL (the library then creates and owns a stream).
+ * *out receives the context.  Errors: MFQ_EINVAL, MFQ_EDEVICE. */
+mfq_status mfq_create(int device, void *hip_stream, mfq_ctx **out);
+
+/* Destroy a context and free what the library allocated (never the caller's
+ * workspace).  NULL is accepted. */
+mfq_status mfq_destroy(mfq_ctx *ctx);
+
+/* Text of the last error on ctx; owned by ctx, valid until the next call on
+ * ctx.  Never NULL. */
+const char *mfq_last_error(const mfq_ctx *ctx);
+
+/* Device workspace, in bytes, that mfq_init_state needs for this problem
+ * (state double buffer, propagator, Gram / Cholesky buffers, scratch). */
+mfq_status mfq_workspace_bytes(const mfq_lattice *lat, int32_t N, int32_t n_traj,
+                               int32_t precision, size_t *bytes);
+
+/* Set up n_traj trajectories of N particles on lattice *lat and put each into
+ * the initial product state of Appendix A: orbital k = e_{occupied[k]}.
+ * occupied: N ascending site ids, or NULL for the Neel state (even sites in
+ * 1d) / checkerboard (x+y even in 2d), which needs N = L/2 and even L.
+ * traj_uid: n_traj host values that key each trajectory's random numbers.
+ * dev_ws: caller-owned device memory of ws_bytes >= mfq_workspace_bytes(),
+ * borrowed until the next init_state or destroy, or NULL to let the library
+ * allocate it.  Resets the step counter to 0.  1 <= N < L, n_traj >= 1.
+ * Errors: MFQ_EINVAL, MFQ_ENOMEM, MFQ_EDEVICE. */
+mfq_status mfq_init_state(mfq_ctx *ctx, const mfq_lattice *lat, int32_t N, int32_t n_traj,
+                          const uint64_t *traj_uid, const int32_t *occupied, int32_t precision,
+                          void *dev_ws, size_t ws_bytes);
+
+/* Advance every trajectory by n_steps steps of length dt with the given
+ * protocol; gamma is a host array of n_traj monitoring rates (>= 0).
+ * Projective: each site is measured with probability min(gamma*dt, 1) per
+ * step; measured sites are projected in ascending order with their
+ * conditional Born probabilities (Appendix A; the paper draws Poisson
+ * waiting times instead).  Homodyne: rows of U are scaled by
+ * exp(xi_i + gamma (2<n_i> - 1) dt), xi_i ~ N(0, gamma dt) (Eq. (A4), applied
+ * after the propagator).  The propagator exp(-i Ht dt) is rebuilt when dt
+ * changes.  Asynchronous; numeric failures (Cholesky breakdown) surface as
+ * MFQ_ENUMERIC from the next synchronising call.
+ * Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_EDEVICE. */
+mfq_status mfq_step(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                    int32_t n_steps);
+
+/* Entanglement entropy S_A (Sec. II) of region A = region[0..n_sites) for
+ * every trajectory: S_host[t], caller-owned, n_traj doubles.  Computed from
+ * the eigenvalues of C_A = U_A U_A^+ (or of U_A^+ U_A when n_sites > N, same
+ * nonzero spectrum), clamped to [0, 1].  Synchronises.
+ * Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_ENUMERIC, MFQ_EDEVICE. */
+mfq_status mfq_entropy(mfq_ctx *ctx, const int32_t *region, int32_t n_sites, double *S_host);
+
+/* Eigenvalues of C_A (ascending, not clamped) for every trajectory:
+ * lam_host[t * m + k], m = min(n_sites, N), caller-owned.  Synchronises. */
+mfq_status mfq_region_spectrum(mfq_ctx *ctx, const int32_t *region, int32_t n_sites,
+                               double *lam_host);
+
+/* Mutual information I2 = S_A + S_B - S_{A u B} (Sec. IV) per trajectory;
+ * A and B must be disjoint.  I_host: n_traj doubles.  Synchronises. */
+mfq_status mfq_mutual_info(mfq_ctx *ctx, const int32_t *A, int32_t nA, const int32_t *B,
+                           int32_t nB, double *I_host);
+
+/* Born probabilities <n_i> = sum_k |U_ik|^2 of the current state (Appendix A):
+ * p_host[t * L + i], caller-owned.  Synchronises. */
+mfq_status mfq_occupations(mfq_ctx *ctx, double *p_host);
+
+/* Projective measurements made by the most recent step: for trajectory t,
+ * counts[t] events (at most max_events are copied), event e at index
+ * t * max_events + e: site, outcome (0/1) and conditional Born probability.
+ * Any of the three output arrays may be NULL.  Synchronises. */
+mfq_status mfq_pm_events(mfq_ctx *ctx, int32_t max_events, int32_t *counts, int32_t *sites,
+                         int32_t *outcomes, double *probs);
+
+/* Checkpoint: copy the current U of all trajectories (L*N*n_traj complex
+ * doubles, layout as above) to host memory and report the absolute step
+ * index.  Synchronises. */
+mfq_status mfq_get_state(mfq_ctx *ctx, void *U_host, int64_t *step);
+
+/* Restore a checkpoint written by mfq_get_state (same problem shape).
+ * Columns must be orthonormal for the physics to hold; the library does not
+ * re-orthonormalise on load. */
+mfq_status mfq_set_state(mfq_ctx *ctx, const void *U_host, int64_t step);
+
+/* Wait for all work on the context's stream; reports deferred numeric errors
+ * (MFQ_ENUMERIC) and clears them. */
+mfq_status mfq_synchronize(mfq_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFQ_H */

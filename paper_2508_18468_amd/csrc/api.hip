@@ -1,0 +1,521 @@
+// C ABI of libmfq: context, device memory plan and the step / observable
+// drivers.  Every arithmetic step runs in the HIP kernels of this library;
+// the host only validates arguments, computes the propagator's generating
+// row (a Bessel series, once per dt) and orders launches on the stream.
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mfq.h"
+#include "mfq_internal.h"
+
+using namespace mfq;
+
+struct mfq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // problem
+  bool ready = false;
+  mfq_lattice lat{};
+  int L = 0, N = 0, B = 0, precision = 0;
+  int64_t step = 0;
+  double dt_cached = NAN;
+  // workspace
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  cplx *X[2] = {nullptr, nullptr};
+  int cur = 0;
+  cplx *P = nullptr, *gx = nullptr, *gy = nullptr;
+  CholWork chol{};
+  EigWork eig{};
+  double *p = nullptr, *gamma = nullptr;
+  uint64_t *uid = nullptr;
+  int *occ = nullptr, *region = nullptr, *flag = nullptr;
+  int *pm_sites = nullptr, *pm_out = nullptr, *pm_cnt = nullptr;
+  double *pm_prob = nullptr;
+  cplx *pm_v = nullptr, *pm_w = nullptr;
+  std::vector<double> gamma_host;
+};
+
+namespace {
+
+mfq_status fail(mfq_ctx *c, mfq_status code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+mfq_status hip_fail(mfq_ctx *c, hipError_t e, const char *where) {
+  return fail(c, MFQ_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, where)                       \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(c, e_, where); \
+  } while (0)
+
+bool lattice_ok(const mfq_lattice *lat) {
+  if (!lat) return false;
+  if (lat->dim == 1) return lat->Lx >= 2 && lat->Lx <= (1 << 20) && std::isfinite(lat->J);
+  if (lat->dim == 2)
+    return lat->Lx >= 2 && lat->Ly >= 2 && (long)lat->Lx * lat->Ly <= (1 << 20) &&
+           std::isfinite(lat->J);
+  return false;
+}
+
+int lattice_L(const mfq_lattice *lat) { return lat->dim == 1 ? lat->Lx : lat->Lx * lat->Ly; }
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte layout of the workspace; `base` may be null (sizing only).
+struct Plan {
+  size_t off = 0;
+  char *base = nullptr;
+  template <class T>
+  T *take(size_t count) {
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+void carve(Plan &pl, int L, int N, int B, mfq_ctx *c) {
+  const size_t LN = (size_t)L * N, NN = (size_t)N * N;
+  cplx *x0 = pl.take<cplx>(LN * B);
+  cplx *x1 = pl.take<cplx>(LN * B);
+  cplx *P = pl.take<cplx>((size_t)L * L);
+  cplx *gx = pl.take<cplx>(L);
+  cplx *gy = pl.take<cplx>(L);
+  cplx *G = pl.take<cplx>(NN * B);
+  cplx *Rinv = pl.take<cplx>(NN * B);
+  cplx *T = pl.take<cplx>((size_t)N * CHOL_NB * B);
+  double *p = pl.take<double>((size_t)L * B);
+  double *gamma = pl.take<double>(B);
+  uint64_t *uid = pl.take<uint64_t>(B);
+  int *occ = pl.take<int>(N);
+  int *region = pl.take<int>(L);
+  int *flag = pl.take<int>(64);
+  int *pm_sites = pl.take<int>((size_t)L * B);
+  int *pm_out = pl.take<int>((size_t)L * B);
+  int *pm_cnt = pl.take<int>(B);
+  double *pm_prob = pl.take<double>((size_t)L * B);
+  cplx *pm_v = pl.take<cplx>((size_t)N * B);
+  cplx *pm_w = pl.take<cplx>((size_t)L * B);
+  cplx *ev = pl.take<cplx>((size_t)N * B);
+  cplx *ew = pl.take<cplx>((size_t)N * B);
+  double *ed = pl.take<double>((size_t)N * B);
+  double *ee = pl.take<double>((size_t)N * B);
+  double *elam = pl.take<double>((size_t)N * B);
+  double *eS = pl.take<double>(B);
+  if (!c) return;
+  c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy;
+  c->chol = CholWork{G, Rinv, T, flag};
+  c->eig = EigWork{G, ev, ew, ed, ee, elam, eS};
+  c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
+  c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
+  c->pm_v = pm_v; c->pm_w = pm_w;
+}
+
+// Generating row of the ring propagator exp(-i Ht dt) from the Jacobi-Anger
+// expansion exp(-i z cos k) = sum_n (-i)^n J_n(z) e^{ink}, z = 2 J dt:
+// g[d] = sum over integers n = d (mod Lr) of (-i)^|n| J_|n|(z).
+void ring_row(int Lr, double J, double dt, std::vector<std::complex<double>> &g) {
+  g.assign(Lr, std::complex<double>(0.0, 0.0));
+  const double z = 2.0 * J * dt, az = std::fabs(z);
+  const std::complex<double> mi(0.0, -1.0);
+  // J_n(|z|) falls below 1e-300 of J_0 long before n = |z| + 80 for |z| <= 100
+  const int nmax = (int)az + 80;
+  std::vector<double> jn(nmax + 1);
+  for (int n = 0; n <= nmax; ++n) {
+    double v = (az == 0.0) ? (n == 0 ? 1.0 : 0.0) : std::cyl_bessel_j((double)n, az);
+    if (z < 0.0 && (n & 1)) v = -v;  // J_n(-x) = (-1)^n J_n(x)
+    jn[n] = v;
+  }
+  for (int n = -nmax; n <= nmax; ++n) {
+    const int an = n < 0 ? -n : n;
+    std::complex<double> ph(1.0, 0.0);
+    switch (an & 3) {
+      case 1: ph = mi; break;
+      case 2: ph = -1.0; break;
+      case 3: ph = -mi; break;
+      default: break;
+    }
+    const int d = ((n % Lr) + Lr) % Lr;
+    g[d] += ph * jn[an];
+  }
+}
+
+mfq_status check_flag(mfq_ctx *c) {
+  int f = 0;
+  HIPCHK(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag read");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  if (f) {
+    HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
+    HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+    return fail(c, MFQ_ENUMERIC, "Cholesky breakdown (non-positive or non-finite pivot)");
+  }
+  return MFQ_OK;
+}
+
+mfq_status build_propagator(mfq_ctx *c, double dt) {
+  std::vector<std::complex<double>> gx, gy;
+  ring_row(c->lat.Lx, c->lat.J, dt, gx);
+  if (c->lat.dim == 2) ring_row(c->lat.Ly, c->lat.J, dt, gy);
+  else gy.assign(1, std::complex<double>(1.0, 0.0));
+  for (auto &z : gx)
+    if (!std::isfinite(z.real()) || !std::isfinite(z.imag()))
+      return fail(c, MFQ_EINVAL, "propagator not finite for this dt");
+  HIPCHK(hipMemcpyAsync(c->gx, gx.data(), gx.size() * sizeof(cplx), hipMemcpyHostToDevice, c->stream),
+         "propagator row upload");
+  HIPCHK(hipMemcpyAsync(c->gy, gy.data(), gy.size() * sizeof(cplx), hipMemcpyHostToDevice, c->stream),
+         "propagator row upload");
+  HIPCHK(expand_propagator(c->P, c->gx, c->gy, c->lat.dim, c->lat.Lx, c->lat.Ly, c->stream),
+         "expand_propagator");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  c->dt_cached = dt;
+  return MFQ_OK;
+}
+
+mfq_status validate_region(mfq_ctx *c, const int32_t *r, int32_t n) {
+  if (n < 0 || n > c->L) return fail(c, MFQ_EINVAL, "region size out of range");
+  if (n > 0 && !r) return fail(c, MFQ_EINVAL, "region is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (r[i] < 0 || r[i] >= c->L) return fail(c, MFQ_EINVAL, "region site out of range");
+    if (i > 0 && r[i] <= r[i - 1]) return fail(c, MFQ_EINVAL, "region not strictly ascending");
+  }
+  return MFQ_OK;
+}
+
+// Eigenvalues of C_A for every trajectory into c->eig.lam; *n_out = their count.
+mfq_status region_spectrum_dev(mfq_ctx *c, const int32_t *region, int32_t n, int *n_out) {
+  mfq_status st = validate_region(c, region, n);
+  if (st) return st;
+  *n_out = 0;
+  if (n == 0) return MFQ_OK;
+  HIPCHK(hipMemcpyAsync(c->region, region, n * sizeof(int), hipMemcpyHostToDevice, c->stream),
+         "region upload");
+  int m = 0;
+  HIPCHK(region_gram(c->X[c->cur], c->L, c->N, c->B, c->region, n, c->eig.A, &m, c->stream),
+         "region_gram");
+  HIPCHK(tridiagonalize(c->eig, m, c->B, c->stream), "tridiagonalize");
+  HIPCHK(bisect_eigvals(c->eig, m, c->B, c->stream), "bisect");
+  *n_out = m;
+  return MFQ_OK;
+}
+
+mfq_status entropy_dev(mfq_ctx *c, const int32_t *region, int32_t n, double *S_host) {
+  int m = 0;
+  mfq_status st = region_spectrum_dev(c, region, n, &m);
+  if (st) return st;
+  if (m == 0) {
+    for (int b = 0; b < c->B; ++b) S_host[b] = 0.0;
+    return MFQ_OK;
+  }
+  HIPCHK(entropy_sum(c->eig, m, c->B, c->stream), "entropy");
+  HIPCHK(hipMemcpyAsync(S_host, c->eig.S, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "entropy download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return MFQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mfq_status mfq_create(int device, void *hip_stream, mfq_ctx **out) {
+  if (!out) return MFQ_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MFQ_EINVAL;
+  mfq_ctx *c = new (std::nothrow) mfq_ctx();
+  if (!c) return MFQ_ENOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return MFQ_EDEVICE;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) {
+      delete c;
+      return MFQ_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return MFQ_OK;
+}
+
+mfq_status mfq_destroy(mfq_ctx *c) {
+  if (!c) return MFQ_OK;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->own_ws && c->ws) hipFree(c->ws);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete c;
+  return MFQ_OK;
+}
+
+const char *mfq_last_error(const mfq_ctx *c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+mfq_status mfq_workspace_bytes(const mfq_lattice *lat, int32_t N, int32_t n_traj, int32_t precision,
+                               size_t *bytes) {
+  if (!lattice_ok(lat) || !bytes || n_traj < 1 || precision != MFQ_FP64) return MFQ_EINVAL;
+  const int L = lattice_L(lat);
+  if (N < 1 || N >= L) return MFQ_EINVAL;
+  Plan pl;
+  carve(pl, L, N, n_traj, nullptr);
+  *bytes = pl.off + 256;
+  return MFQ_OK;
+}
+
+mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t n_traj,
+                          const uint64_t *traj_uid, const int32_t *occupied, int32_t precision,
+                          void *dev_ws, size_t ws_bytes) {
+  if (!c) return MFQ_EINVAL;
+  c->ready = false;
+  if (!lattice_ok(lat)) return fail(c, MFQ_EINVAL, "invalid lattice");
+  if (precision != MFQ_FP64) return fail(c, MFQ_EINVAL, "unsupported precision");
+  const int L = lattice_L(lat);
+  if (N < 1 || N >= L) return fail(c, MFQ_EINVAL, "need 1 <= N < L");
+  if (n_traj < 1 || n_traj > 65535) return fail(c, MFQ_EINVAL, "need 1 <= n_traj <= 65535");
+  if (!traj_uid) return fail(c, MFQ_EINVAL, "traj_uid is NULL");
+  std::vector<int> occ(N);
+  if (occupied) {
+    for (int k = 0; k < N; ++k) {
+      occ[k] = occupied[k];
+      if (occ[k] < 0 || occ[k] >= L || (k > 0 && occ[k] <= occ[k - 1]))
+        return fail(c, MFQ_EINVAL, "occupied sites must be ascending and in [0, L)");
+    }
+  } else {
+    if (2 * N != L) return fail(c, MFQ_EINVAL, "default (Neel) state needs N = L/2");
+    if (lat->dim == 1 && L % 2) return fail(c, MFQ_EINVAL, "Neel state needs even L");
+    if (lat->dim == 2 && (lat->Lx % 2 || lat->Ly % 2))
+      return fail(c, MFQ_EINVAL, "checkerboard state needs even Lx and Ly");
+    int k = 0;
+    for (int i = 0; i < L; ++i) {
+      const int x = i % lat->Lx, y = i / lat->Lx;
+      if ((x + y) % 2 == 0) occ[k++] = i;
+    }
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, MFQ_EDEVICE, "hipSetDevice");
+  Plan sizing;
+  carve(sizing, L, N, n_traj, nullptr);
+  const size_t need = sizing.off + 256;
+  if (c->own_ws && c->ws) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->own_ws = false;
+  }
+  if (dev_ws) {
+    if (ws_bytes < need) return fail(c, MFQ_ENOMEM, "workspace too small");
+    c->ws = dev_ws;
+    c->ws_bytes = ws_bytes;
+  } else {
+    if (hipMalloc(&c->ws, need) != hipSuccess) {
+      c->ws = nullptr;
+      return fail(c, MFQ_ENOMEM, "hipMalloc of the workspace failed");
+    }
+    c->own_ws = true;
+    c->ws_bytes = need;
+  }
+  Plan pl;
+  pl.base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws)));
+  carve(pl, L, N, n_traj, c);
+  c->lat = *lat;
+  c->L = L; c->N = N; c->B = n_traj; c->precision = precision;
+  c->step = 0; c->cur = 0; c->dt_cached = NAN;
+  c->gamma_host.assign(n_traj, -1.0);
+  HIPCHK(hipMemcpyAsync(c->uid, traj_uid, n_traj * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream),
+         "uid upload");
+  HIPCHK(hipMemcpyAsync(c->occ, occ.data(), N * sizeof(int), hipMemcpyHostToDevice, c->stream),
+         "occupied upload");
+  HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
+  HIPCHK(fill_zero(c->pm_cnt, ((size_t)n_traj * sizeof(int) + 7) / 8 * 8, c->stream), "event clear");
+  HIPCHK(init_state(c->X[0], L, N, n_traj, c->occ, c->stream), "init_state");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  c->ready = true;
+  return MFQ_OK;
+}
+
+mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                    int32_t n_steps) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (protocol != MFQ_PROJECTIVE && protocol != MFQ_HOMODYNE) return fail(c, MFQ_EINVAL, "bad protocol");
+  if (!gamma) return fail(c, MFQ_EINVAL, "gamma is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, MFQ_EINVAL, "dt must be positive and finite");
+  if (n_steps < 0) return fail(c, MFQ_EINVAL, "n_steps < 0");
+  for (int b = 0; b < c->B; ++b)
+    if (!(gamma[b] >= 0.0) || !std::isfinite(gamma[b])) return fail(c, MFQ_EINVAL, "gamma must be >= 0");
+  if (n_steps == 0) return MFQ_OK;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (!(dt == c->dt_cached)) {
+    mfq_status st = build_propagator(c, dt);
+    if (st) return st;
+  }
+  if (std::memcmp(c->gamma_host.data(), gamma, c->B * sizeof(double)) != 0) {
+    std::memcpy(c->gamma_host.data(), gamma, c->B * sizeof(double));
+    HIPCHK(hipMemcpyAsync(c->gamma, c->gamma_host.data(), c->B * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream), "gamma upload");
+  }
+  const int L = c->L, N = c->N, B = c->B;
+  for (int s = 0; s < n_steps; ++s) {
+    const int64_t n = c->step + 1;
+    cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
+    // propagator: Xb = P Xa, the batch as one L x (N*B) matrix
+    GemmDesc g{};
+    g.M = L; g.N = N * B; g.K = L; g.batch = 1;
+    g.A = c->P; g.lda = L; g.opA = OP_N;
+    g.B = Xa; g.ldb = L; g.opB = OP_N;
+    g.D = Xb; g.ldd = L;
+    g.alpha = cplx{1.0, 0.0};
+    HIPCHK(zgemm(g, c->stream), "propagator gemm");
+    if (protocol == MFQ_HOMODYNE) {
+      HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, n, c->stream), "homodyne");
+    } else {
+      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, n, c->pm_sites, c->pm_out,
+                        c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
+    }
+    HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, c->stream), "cholqr pass 1");
+    HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, c->stream), "cholqr pass 2");
+    c->cur = 1 - c->cur;
+    c->step = n;
+  }
+  return MFQ_OK;
+}
+
+mfq_status mfq_entropy(mfq_ctx *c, const int32_t *region, int32_t n_sites, double *S_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!S_host) return fail(c, MFQ_EINVAL, "S_host is NULL");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  mfq_status st = entropy_dev(c, region, n_sites, S_host);
+  if (st) return st;
+  return check_flag(c);
+}
+
+mfq_status mfq_region_spectrum(mfq_ctx *c, const int32_t *region, int32_t n_sites, double *lam_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!lam_host) return fail(c, MFQ_EINVAL, "lam_host is NULL");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  int m = 0;
+  mfq_status st = region_spectrum_dev(c, region, n_sites, &m);
+  if (st) return st;
+  if (m > 0)
+    HIPCHK(hipMemcpyAsync(lam_host, c->eig.lam, (size_t)m * c->B * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream), "spectrum download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return check_flag(c);
+}
+
+mfq_status mfq_mutual_info(mfq_ctx *c, const int32_t *A, int32_t nA, const int32_t *B, int32_t nB,
+                           double *I_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!I_host) return fail(c, MFQ_EINVAL, "I_host is NULL");
+  mfq_status st = validate_region(c, A, nA);
+  if (st) return st;
+  if ((st = validate_region(c, B, nB))) return st;
+  std::vector<int32_t> AB;
+  AB.reserve(nA + nB);
+  int i = 0, j = 0;
+  while (i < nA || j < nB) {
+    if (j >= nB || (i < nA && A[i] < B[j])) AB.push_back(A[i++]);
+    else if (i >= nA || B[j] < A[i]) AB.push_back(B[j++]);
+    else return fail(c, MFQ_EINVAL, "regions A and B overlap");
+  }
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  std::vector<double> sa(c->B), sb(c->B), sab(c->B);
+  if ((st = entropy_dev(c, A, nA, sa.data()))) return st;
+  if ((st = entropy_dev(c, B, nB, sb.data()))) return st;
+  if ((st = entropy_dev(c, AB.data(), (int32_t)AB.size(), sab.data()))) return st;
+  for (int b = 0; b < c->B; ++b) I_host[b] = sa[b] + sb[b] - sab[b];
+  return check_flag(c);
+}
+
+mfq_status mfq_occupations(mfq_ctx *c, double *p_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!p_host) return fail(c, MFQ_EINVAL, "p_host is NULL");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(born_only(c->X[c->cur], c->p, c->L, c->N, c->B, c->stream), "born");
+  HIPCHK(hipMemcpyAsync(p_host, c->p, (size_t)c->L * c->B * sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream), "occupations download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return check_flag(c);
+}
+
+mfq_status mfq_pm_events(mfq_ctx *c, int32_t max_events, int32_t *counts, int32_t *sites,
+                         int32_t *outcomes, double *probs) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (max_events < 0 || !counts) return fail(c, MFQ_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int L = c->L, B = c->B;
+  std::vector<int> cnt(B), st(max_events > 0 ? (size_t)L * B : 0), oc(st.size());
+  std::vector<double> pr(st.size());
+  HIPCHK(hipMemcpyAsync(cnt.data(), c->pm_cnt, B * sizeof(int), hipMemcpyDeviceToHost, c->stream), "events");
+  if (max_events > 0) {
+    HIPCHK(hipMemcpyAsync(st.data(), c->pm_sites, st.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream), "events");
+    HIPCHK(hipMemcpyAsync(oc.data(), c->pm_out, oc.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream), "events");
+    HIPCHK(hipMemcpyAsync(pr.data(), c->pm_prob, pr.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream), "events");
+  }
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  for (int b = 0; b < B; ++b) {
+    counts[b] = cnt[b];
+    const int m = std::min(cnt[b], max_events);
+    for (int e = 0; e < m; ++e) {
+      if (sites) sites[(size_t)b * max_events + e] = st[(size_t)b * L + e];
+      if (outcomes) outcomes[(size_t)b * max_events + e] = oc[(size_t)b * L + e];
+      if (probs) probs[(size_t)b * max_events + e] = pr[(size_t)b * L + e];
+    }
+  }
+  return MFQ_OK;
+}
+
+mfq_status mfq_get_state(mfq_ctx *c, void *U_host, int64_t *step) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (U_host)
+    HIPCHK(hipMemcpyAsync(U_host, c->X[c->cur], (size_t)c->L * c->N * c->B * sizeof(cplx),
+                          hipMemcpyDeviceToHost, c->stream), "state download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  if (step) *step = c->step;
+  return check_flag(c);
+}
+
+mfq_status mfq_set_state(mfq_ctx *c, const void *U_host, int64_t step) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!U_host || step < 0) return fail(c, MFQ_EINVAL, "bad arguments");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(c->X[c->cur], U_host, (size_t)c->L * c->N * c->B * sizeof(cplx),
+                        hipMemcpyHostToDevice, c->stream), "state upload");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  c->step = step;
+  return MFQ_OK;
+}
+
+mfq_status mfq_synchronize(mfq_ctx *c) {
+  if (!c) return MFQ_EINVAL;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  if (!c->ready) return MFQ_OK;
+  return check_flag(c);
+}
+
+}  // extern "C"
