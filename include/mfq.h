@@ -58,6 +58,10 @@ typedef int32_t mfq_status;
 #define MFQ_HOMODYNE 1    /* homodyne / quantum state diffusion, Eq. (A4) (QSD) */
 
 #define MFQ_FP64 0        /* every step in FP64 */
+#define MFQ_FP32_BULK 1   /* propagator product in FP32 on the matrix cores, written as
+                             U + (P - I) U with the identity term in FP64; Born
+                             probabilities, homodyne / projective updates, Cholesky-QR2
+                             and the eigensolver in FP64 */
 
 /* Lattice of Sec. II (1d ring) or Sec. IV (2d torus); periodic boundaries,
  * nearest-neighbour hopping Ht_ij = J.  dim = 1: L = Lx (Ly ignored);
@@ -156,6 +160,22 @@ mfq_status mfq_set_state(mfq_ctx *ctx, const void *U_host, int64_t step);
 /* Wait for all work on the context's stream; reports deferred numeric errors
  * (MFQ_ENUMERIC) and clears them. */
 mfq_status mfq_synchronize(mfq_ctx *ctx);
+
+/* Phase timing with HIP events recorded on the context's stream around each
+ * phase of a step (no extra synchronisation while enabled). */
+#define MFQ_PHASE_PROPAGATE 0 /* propagator GEMM U <- P U: exactly one kernel launch per step */
+#define MFQ_PHASE_MEASURE 1   /* Born probabilities + homodyne factor, or projective measurement */
+#define MFQ_PHASE_REORTH 2    /* both Cholesky-QR passes */
+#define MFQ_PHASE_OBSERVE 3   /* region Gram, tridiagonalisation, bisection, entropy */
+#define MFQ_NPHASES 4
+
+/* enable != 0 starts timing (and clears accumulated times); 0 stops it. */
+mfq_status mfq_profile(mfq_ctx *ctx, int32_t enable);
+
+/* Accumulated milliseconds and number of timed intervals per phase since
+ * timing was enabled; ms and count are host arrays of MFQ_NPHASES entries
+ * (either may be NULL).  Synchronises. */
+mfq_status mfq_phase_times(mfq_ctx *ctx, double *ms, int64_t *count);
 
 #ifdef __cplusplus
 }

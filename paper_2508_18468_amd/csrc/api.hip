@@ -32,6 +32,7 @@ struct mfq_ctx {
   cplx *X[2] = {nullptr, nullptr};
   int cur = 0;
   cplx *P = nullptr, *gx = nullptr, *gy = nullptr;
+  float *Pr32 = nullptr, *Pi32 = nullptr;  // FP32-bulk: planes of P - I
   CholWork chol{};
   EigWork eig{};
   double *p = nullptr, *gamma = nullptr;
@@ -41,6 +42,13 @@ struct mfq_ctx {
   double *pm_prob = nullptr;
   cplx *pm_v = nullptr, *pm_w = nullptr;
   std::vector<double> gamma_host;
+  // phase timing
+  bool profiling = false;
+  std::vector<hipEvent_t> events;     // pool, reused after every read-out
+  size_t events_used = 0;
+  std::vector<int> rec_phase;         // interval i: phase, events 2i and 2i+1
+  double phase_ms[MFQ_NPHASES] = {0, 0, 0, 0};
+  int64_t phase_n[MFQ_NPHASES] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -85,7 +93,7 @@ struct Plan {
   }
 };
 
-void carve(Plan &pl, int L, int N, int B, mfq_ctx *c) {
+void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   const size_t LN = (size_t)L * N, NN = (size_t)N * N;
   cplx *x0 = pl.take<cplx>(LN * B);
   cplx *x1 = pl.take<cplx>(LN * B);
@@ -113,9 +121,12 @@ void carve(Plan &pl, int L, int N, int B, mfq_ctx *c) {
   double *ee = pl.take<double>((size_t)N * B);
   double *elam = pl.take<double>((size_t)N * B);
   double *eS = pl.take<double>(B);
+  float *pr32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
+  float *pi32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   if (!c) return;
+  c->Pr32 = pr32; c->Pi32 = pi32;
   c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy;
-  c->chol = CholWork{G, Rinv, T, flag};
+  c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
   c->eig = EigWork{G, ev, ew, ed, ee, elam, eS};
   c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
   c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
@@ -151,6 +162,42 @@ void ring_row(int Lr, double J, double dt, std::vector<std::complex<double>> &g)
   }
 }
 
+// Record an event on the stream (phase timing); returns false on failure.
+bool record_event(mfq_ctx *c) {
+  if (c->events_used == c->events.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return false;
+    c->events.push_back(e);
+  }
+  return hipEventRecord(c->events[c->events_used++], c->stream) == hipSuccess;
+}
+
+struct PhaseTimer {
+  mfq_ctx *c;
+  int phase;
+  bool on;
+  PhaseTimer(mfq_ctx *c_, int ph) : c(c_), phase(ph), on(c_->profiling) {
+    if (on) on = record_event(c);
+  }
+  ~PhaseTimer() {
+    if (on && record_event(c)) c->rec_phase.push_back(phase);
+    else if (on) c->events_used--;
+  }
+};
+
+mfq_status collect_phase_times(mfq_ctx *c) {
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  for (size_t i = 0; i < c->rec_phase.size(); ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->events[2 * i], c->events[2 * i + 1]), "event time");
+    c->phase_ms[c->rec_phase[i]] += ms;
+    c->phase_n[c->rec_phase[i]] += 1;
+  }
+  c->rec_phase.clear();
+  c->events_used = 0;
+  return MFQ_OK;
+}
+
 mfq_status check_flag(mfq_ctx *c) {
   int f = 0;
   HIPCHK(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag read");
@@ -177,6 +224,8 @@ mfq_status build_propagator(mfq_ctx *c, double dt) {
          "propagator row upload");
   HIPCHK(expand_propagator(c->P, c->gx, c->gy, c->lat.dim, c->lat.Lx, c->lat.Ly, c->stream),
          "expand_propagator");
+  if (c->precision == MFQ_FP32_BULK)
+    HIPCHK(make_delta_planes(c->P, c->Pr32, c->Pi32, c->L, c->stream), "delta planes");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   c->dt_cached = dt;
   return MFQ_OK;
@@ -198,6 +247,7 @@ mfq_status region_spectrum_dev(mfq_ctx *c, const int32_t *region, int32_t n, int
   if (st) return st;
   *n_out = 0;
   if (n == 0) return MFQ_OK;
+  PhaseTimer t(c, MFQ_PHASE_OBSERVE);
   HIPCHK(hipMemcpyAsync(c->region, region, n * sizeof(int), hipMemcpyHostToDevice, c->stream),
          "region upload");
   int m = 0;
@@ -217,7 +267,10 @@ mfq_status entropy_dev(mfq_ctx *c, const int32_t *region, int32_t n, double *S_h
     for (int b = 0; b < c->B; ++b) S_host[b] = 0.0;
     return MFQ_OK;
   }
-  HIPCHK(entropy_sum(c->eig, m, c->B, c->stream), "entropy");
+  {
+    PhaseTimer t(c, MFQ_PHASE_OBSERVE);
+    HIPCHK(entropy_sum(c->eig, m, c->B, c->stream), "entropy");
+  }
   HIPCHK(hipMemcpyAsync(S_host, c->eig.S, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream),
          "entropy download");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
@@ -255,10 +308,11 @@ mfq_status mfq_create(int device, void *hip_stream, mfq_ctx **out) {
 
 mfq_status mfq_destroy(mfq_ctx *c) {
   if (!c) return MFQ_OK;
-  hipSetDevice(c->device);
-  if (c->stream) hipStreamSynchronize(c->stream);
-  if (c->own_ws && c->ws) hipFree(c->ws);
-  if (c->own_stream) hipStreamDestroy(c->stream);
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return MFQ_OK;
 }
@@ -270,11 +324,12 @@ const char *mfq_last_error(const mfq_ctx *c) {
 
 mfq_status mfq_workspace_bytes(const mfq_lattice *lat, int32_t N, int32_t n_traj, int32_t precision,
                                size_t *bytes) {
-  if (!lattice_ok(lat) || !bytes || n_traj < 1 || precision != MFQ_FP64) return MFQ_EINVAL;
+  if (!lattice_ok(lat) || !bytes || n_traj < 1 || (precision != MFQ_FP64 && precision != MFQ_FP32_BULK))
+    return MFQ_EINVAL;
   const int L = lattice_L(lat);
   if (N < 1 || N >= L) return MFQ_EINVAL;
   Plan pl;
-  carve(pl, L, N, n_traj, nullptr);
+  carve(pl, L, N, n_traj, precision, nullptr);
   *bytes = pl.off + 256;
   return MFQ_OK;
 }
@@ -285,7 +340,8 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   if (!c) return MFQ_EINVAL;
   c->ready = false;
   if (!lattice_ok(lat)) return fail(c, MFQ_EINVAL, "invalid lattice");
-  if (precision != MFQ_FP64) return fail(c, MFQ_EINVAL, "unsupported precision");
+  if (precision != MFQ_FP64 && precision != MFQ_FP32_BULK)
+    return fail(c, MFQ_EINVAL, "unsupported precision");
   const int L = lattice_L(lat);
   if (N < 1 || N >= L) return fail(c, MFQ_EINVAL, "need 1 <= N < L");
   if (n_traj < 1 || n_traj > 65535) return fail(c, MFQ_EINVAL, "need 1 <= n_traj <= 65535");
@@ -310,11 +366,11 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   }
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MFQ_EDEVICE, "hipSetDevice");
   Plan sizing;
-  carve(sizing, L, N, n_traj, nullptr);
+  carve(sizing, L, N, n_traj, precision, nullptr);
   const size_t need = sizing.off + 256;
   if (c->own_ws && c->ws) {
-    hipStreamSynchronize(c->stream);
-    hipFree(c->ws);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ws);
     c->ws = nullptr;
     c->own_ws = false;
   }
@@ -332,7 +388,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   }
   Plan pl;
   pl.base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws)));
-  carve(pl, L, N, n_traj, c);
+  carve(pl, L, N, n_traj, precision, c);
   c->lat = *lat;
   c->L = L; c->N = N; c->B = n_traj; c->precision = precision;
   c->step = 0; c->cur = 0; c->dt_cached = NAN;
@@ -381,15 +437,27 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     g.B = Xa; g.ldb = L; g.opB = OP_N;
     g.D = Xb; g.ldd = L;
     g.alpha = cplx{1.0, 0.0};
-    HIPCHK(zgemm(g, c->stream), "propagator gemm");
-    if (protocol == MFQ_HOMODYNE) {
-      HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, n, c->stream), "homodyne");
-    } else {
-      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, n, c->pm_sites, c->pm_out,
-                        c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
+    {
+      PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
+      if (c->precision == MFQ_FP32_BULK)
+        HIPCHK(propagator_delta_f32(c->Pr32, c->Pi32, Xa, Xb, L, N * B, c->stream), "propagator f32");
+      else
+        HIPCHK(zgemm_propagator(g, c->stream), "propagator gemm");
     }
-    HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, c->stream), "cholqr pass 1");
-    HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, c->stream), "cholqr pass 2");
+    {
+      PhaseTimer t(c, MFQ_PHASE_MEASURE);
+      if (protocol == MFQ_HOMODYNE) {
+        HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, n, c->stream), "homodyne");
+      } else {
+        HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, n, c->pm_sites, c->pm_out,
+                          c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
+      }
+    }
+    {
+      PhaseTimer t(c, MFQ_PHASE_REORTH);
+      HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, false, c->stream), "cholqr pass 1");
+      HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, true, c->stream), "cholqr pass 2");
+    }
     c->cur = 1 - c->cur;
     c->step = n;
   }
@@ -516,6 +584,37 @@ mfq_status mfq_synchronize(mfq_ctx *c) {
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   if (!c->ready) return MFQ_OK;
   return check_flag(c);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+mfq_status mfq_profile(mfq_ctx *c, int32_t enable) {
+  if (!c) return MFQ_EINVAL;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (enable) {
+    mfq_status st = collect_phase_times(c);
+    if (st) return st;
+    for (int i = 0; i < MFQ_NPHASES; ++i) {
+      c->phase_ms[i] = 0.0;
+      c->phase_n[i] = 0;
+    }
+  }
+  c->profiling = enable != 0;
+  return MFQ_OK;
+}
+
+mfq_status mfq_phase_times(mfq_ctx *c, double *ms, int64_t *count) {
+  if (!c) return MFQ_EINVAL;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  mfq_status st = collect_phase_times(c);
+  if (st) return st;
+  for (int i = 0; i < MFQ_NPHASES; ++i) {
+    if (ms) ms[i] = c->phase_ms[i];
+    if (count) count[i] = c->phase_n[i];
+  }
+  return MFQ_OK;
 }
 
 }  // extern "C"

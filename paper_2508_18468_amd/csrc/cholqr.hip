@@ -21,7 +21,9 @@ constexpr int NB = CHOL_NB;
 // write R_JJ back into G and R_JJ^{-1} (full block, zeros below the diagonal)
 // into Rinv[b].  A non-positive or non-finite pivot raises *flag.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, int N, int c0, int w,
-                                                         int *flag) {
+                                                         int *flag, const double *skip_if_le,
+                                                         double skip_thr) {
+  if (skip_if_le && *skip_if_le <= skip_thr) return;
   const int b = blockIdx.x, tid = threadIdx.x;
   cplx *Gb = G + (long)b * N * N;
   cplx *Rb = Rinv + (long)b * N * N;
@@ -86,6 +88,44 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
   if (tid == 0 && bad) atomicOr(flag, 1);
 }
 
+// E = G - I over the upper triangle of every Gram: writes the first-order
+// inverse factor R^{-1} = I - triu(E, 1) - diag(E)/2 and raises *maxdev to the
+// largest |E_ij| (non-negative doubles order like their bit patterns; a NaN
+// compares above every finite value and so selects the full factorisation).
+__global__ __launch_bounds__(256) void near_identity_kernel(const cplx *G, cplx *Rinv, int N,
+                                                            double *maxdev) {
+  const int c = blockIdx.x, b = blockIdx.y;  // one column of one Gram per workgroup
+  const long NN = (long)N * N;
+  const cplx *Gc = G + b * NN + (long)c * N;
+  cplx *Rc = Rinv + b * NN + (long)c * N;
+  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+  double m = 0.0;
+  for (int r = threadIdx.x; r < N; r += 256) {
+    cplx out{0.0, 0.0};
+    if (r <= c) {
+      const cplx e = Gc[r];
+      const double d = (r == c) ? e.re - 1.0 : e.re;
+      const double a = fabs(d) + fabs(e.im);
+      m = (!(a <= 1e300) || m != m) ? qnan : fmax(m, a);
+      out = (r == c) ? cplx{1.0 - 0.5 * d, 0.0} : cplx{-e.re, -e.im};
+    }
+    Rc[r] = out;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double x = red[threadIdx.x], y = red[threadIdx.x + o];
+      red[threadIdx.x] = (x != x || y != y) ? qnan : fmax(x, y);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long *>(maxdev),
+              (unsigned long long)__double_as_longlong(red[0]));
+}
+
 GemmDesc desc() {
   GemmDesc g{};
   g.alpha = cplx{1.0, 0.0};
@@ -96,9 +136,13 @@ GemmDesc desc() {
 }  // namespace
 
 hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &wk,
-                       hipStream_t s) {
+                       bool near_identity, hipStream_t s) {
   hipError_t e;
   const long NN = (long)N * N;
+  // full-factorisation launches are skipped on the device when the near-identity
+  // test passed (max |E| <= threshold)
+  const double *skip = near_identity ? wk.dev : nullptr;
+  const double thr = CHOL_FIRST_ORDER_MAX;
   // G = Uin^+ Uin (upper triangle)
   {
     GemmDesc g = desc();
@@ -109,10 +153,16 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     g.tri = TRI_UPPER;
     if ((e = zgemm(g, s)) != hipSuccess) return e;
   }
+  if (near_identity) {
+    if ((e = fill_zero(wk.dev, sizeof(double), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(near_identity_kernel, dim3(N, B), dim3(256), 0, s, wk.G, wk.Rinv, N, wk.dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const int nJ = (N + NB - 1) / NB;
   for (int J = 0; J < nJ; ++J) {
     const int c0 = J * NB, w = std::min(NB, N - c0);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(B), dim3(256), 0, s, wk.G, wk.Rinv, N, c0, w, wk.flag);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(B), dim3(256), 0, s, wk.G, wk.Rinv, N, c0, w, wk.flag,
+                       skip, thr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int r0 = c0 + w, nr = N - r0;
     if (nr <= 0) break;
@@ -120,6 +170,7 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     // workgroup reads its whole column panel before writing it)
     {
       GemmDesc g = desc();
+      g.skip_if_le = skip; g.skip_thr = thr;
       g.M = w; g.N = nr; g.K = w; g.batch = B;
       g.A = wk.Rinv + c0 + (long)c0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
       g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
@@ -129,6 +180,7 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     // trailing: G_rest,rest -= R_J,rest^+ R_J,rest (upper)
     {
       GemmDesc g = desc();
+      g.skip_if_le = skip; g.skip_thr = thr;
       g.M = nr; g.N = nr; g.K = w; g.batch = B;
       g.A = wk.G + c0 + (long)r0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
       g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
@@ -145,6 +197,7 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     const int c0 = J * NB, w = std::min(NB, N - c0);
     {
       GemmDesc g = desc();
+      g.skip_if_le = skip; g.skip_thr = thr;
       g.M = c0; g.N = w; g.K = c0; g.batch = B;
       g.A = wk.Rinv; g.lda = N; g.sA = NN; g.opA = OP_N; g.aUpper = 1;
       g.B = wk.G + (long)c0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
@@ -153,6 +206,7 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     }
     {
       GemmDesc g = desc();
+      g.skip_if_le = skip; g.skip_thr = thr;
       g.M = c0; g.N = w; g.K = w; g.batch = B;
       g.A = wk.T; g.lda = N; g.sA = (long)N * NB; g.opA = OP_N;
       g.B = wk.Rinv + c0 + (long)c0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;

@@ -28,9 +28,20 @@ struct GemmDesc {
   int tri;                 // TRI_UPPER: only tiles touching the upper triangle of D
   int aUpper;              // op(A) is upper triangular: A[m][k] = 0 for k < m
   int bUpper;              // op(B) is upper triangular: B[k][n] = 0 for k > n
+  const double *skip_if_le;  // if set and *skip_if_le <= skip_thr, the launch does nothing
+  double skip_thr;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
+// Same contraction (op N, op N), launched under a distinct kernel name.
+hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s);
+
+// FP32-bulk propagator U' = U + (P - I) U: planes of P - I in FP32, product on
+// the FP32 matrix cores, identity term and output in FP64.  U and D are
+// column-major L x ncols (ld = L) and must not overlap.
+hipError_t make_delta_planes(const cplx *P, float *Pr, float *Pi, int L, hipStream_t s);
+hipError_t propagator_delta_f32(const float *Pr, const float *Pi, const cplx *U, cplx *D, int L,
+                                int ncols, hipStream_t s);
 
 // ---------------------------------------------------------------- state kernels
 hipError_t expand_propagator(cplx *P, const cplx *gx, const cplx *gy, int dim, int Lx, int Ly,
@@ -46,15 +57,22 @@ hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- Cholesky-QR
 struct CholWork {
-  cplx *G;      // N x N per trajectory (upper triangle used)
-  cplx *Rinv;   // N x N per trajectory
-  cplx *T;      // N x NB per trajectory
-  int *flag;    // device error flag
+  cplx *G;       // N x N per trajectory (upper triangle used)
+  cplx *Rinv;    // N x N per trajectory
+  cplx *T;       // N x NB per trajectory
+  int *flag;     // device error flag
+  double *dev;   // device scalar: max |G - I| of the latest near-identity check
 };
 constexpr int CHOL_NB = 64;
-// One Cholesky-QR pass: Uout = Uin * R^{-1}, R = chol(Uin^+ Uin).
+// Largest |U^+ U - I| entry for which the second pass uses the first-order factor.
+constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
+// One Cholesky-QR pass: Uout = Uin * R^{-1}, R = chol(Uin^+ Uin).  With
+// near_identity, the Gram is first tested against I: if every entry of
+// E = G - I is below CHOL_FIRST_ORDER_MAX, R^{-1} = I - triu(E) + diag(E)/2 (the
+// Cholesky factor of I + E to O(|E|^2), i.e. to rounding); otherwise the full
+// factorisation runs.  The choice is made on the device.
 hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &w,
-                       hipStream_t s);
+                       bool near_identity, hipStream_t s);
 
 // ---------------------------------------------------------------- eigen / entropy
 struct EigWork {

@@ -11,11 +11,20 @@
 // de-interleaved into separate LDS planes so that each MFMA operand is one
 // double per lane.
 //
-// Tiling: a 256-thread workgroup (4 wave64) owns a 64 x 64 complex tile of D;
-// each wave owns a 32 x 32 quadrant = 2 x 2 MFMA blocks, with separate real and
-// imaginary accumulators (8 x 4 doubles per lane).  K advances in chunks of 16
-// through double-buffered LDS (64 KiB); the next chunk is fetched into
-// registers while the current one feeds the matrix cores.
+// Tiling: a workgroup owns an MT x NT complex tile of D; its wave64s form a
+// 2 x (NT/32) grid and each owns a block of 16 x 16 MFMA outputs with separate
+// real and imaginary accumulators.  Two shapes:
+//   64 x 64,   4 waves, 32 x 32 per wave   small or thin contractions;
+//   128 x 128, 8 waves, 64 x 32 per wave   the large ones: half the L2->CU
+//              bytes per flop of the small tile, 64 accumulator doubles per
+//              lane (more per wave would overflow the register file).
+// K advances in chunks of 16 through double-buffered LDS; the next chunk is
+// fetched into registers while the current one feeds the matrix cores.
+//
+// Workgroup -> tile mapping is XCD-aware: the dispatcher hands workgroup i to
+// XCD i mod 8, so the 1-D grid is ordered such that all tiles of one batch
+// entry (or, for a single wide matrix, all row tiles of one column panel) run
+// on the same XCD and share its L2.
 //
 // MFMA lane layout (gfx950, checked on hardware): operand A lane l holds
 // A[l % 16][l / 16], operand B holds B[l / 16][l % 16]; output register r of
@@ -28,11 +37,68 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int MT = 64, NT = 64, KT = 16, PAD = 1;
+constexpr int PAD = 1, NXCD = 8;
 
-template <int OPA, int OPB>
-__global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
-  const int tm = blockIdx.x, tn = blockIdx.y, b = blockIdx.z;
+struct TileMap {
+  int tilesM, tilesN, groups, per_group;  // group = batch entry, or (batch, column panel)
+  bool by_panel, upper;                   // upper: only tiles with tm <= tn are launched
+  bool linear;                            // fewer groups than XCDs: plain linear order
+};
+
+__host__ __device__ inline TileMap make_map(int M, int N, int batch, int MT, int NT, int tri) {
+  TileMap t;
+  t.tilesM = (M + MT - 1) / MT;
+  t.tilesN = (N + NT - 1) / NT;
+  t.upper = tri == TRI_UPPER && MT == NT && t.tilesM == t.tilesN;
+  t.by_panel = !t.upper && batch < NXCD;
+  t.groups = t.by_panel ? batch * t.tilesN : batch;
+  t.per_group = t.by_panel ? t.tilesM
+              : t.upper ? t.tilesM * (t.tilesM + 1) / 2 : t.tilesM * t.tilesN;
+#ifdef MFQ_LINEAR_TILE_MAP
+  t.linear = true;
+#else
+  t.linear = t.groups < NXCD;
+#endif
+  return t;
+}
+
+// Index t of the upper-triangle tiles, column by column: (0,0), (0,1), (1,1), (0,2), ...
+__device__ inline void upper_tile(int t, int &tm, int &tn) {
+  int c = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (c * (c + 1) / 2 > t) --c;
+  while ((c + 1) * (c + 2) / 2 <= t) ++c;
+  tn = c;
+  tm = t - c * (c + 1) / 2;
+}
+
+// GATHER: storage rows of A / B are looked up through idxA / idxB.
+// EDGE: bounds-checked loads and stores (M, N or K not multiples of the tile).
+template <int OPA, int OPB, int MT, int NT, int KT, bool GATHER, bool EDGE>
+__device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
+  // waves: 2 along M; NT/32 along N (2 for 64x64 tiles, 4 for 128x128 tiles)
+  constexpr int WM = 2, WN = NT / 32, NTHR = 64 * WM * WN;
+  constexpr int IM = MT / WM / 16, JN = NT / WN / 16;  // 16x16 blocks per wave
+  constexpr int LA = MT * KT / NTHR, LB = NT * KT / NTHR;
+  if (g.skip_if_le && *g.skip_if_le <= g.skip_thr) return;
+  const TileMap map = make_map(g.M, g.N, g.batch, MT, NT, g.tri);
+  const int id = blockIdx.x;
+  const int k_on_xcd = map.linear ? id : id / NXCD;
+  const int grp = map.linear ? id / map.per_group : id % NXCD + NXCD * (k_on_xcd / map.per_group);
+  const int t = k_on_xcd % map.per_group;
+  if (grp >= map.groups) return;
+  int b, tm, tn;
+  if (map.by_panel) {
+    b = grp / map.tilesN;
+    tn = grp % map.tilesN;
+    tm = t;
+  } else if (map.upper) {
+    b = grp;
+    upper_tile(t, tm, tn);
+  } else {
+    b = grp;
+    tm = t % map.tilesM;
+    tn = t / map.tilesM;
+  }
   const int m0 = tm * MT, n0 = tn * NT;
   if (g.tri == TRI_UPPER && m0 > n0 + NT - 1) return;  // tile entirely below the diagonal
   int kbeg = 0, kend = g.K;
@@ -43,78 +109,85 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
   __shared__ double Br[2][KT][NT + PAD], Bi[2][KT][NT + PAD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1;
+  const int wr = wave % WM, wc = wave / WM;
   const cplx *A = g.A + (long)b * g.sA;
   const cplx *B = g.B + (long)b * g.sB;
 
-  double ra_re[4], ra_im[4], rb_re[4], rb_im[4];
+  // per-thread tile coordinates: element i of this thread is (m_a, k_a + i*da) of the
+  // A tile and (k_b + i*db, n_b) of the B tile
+  constexpr int DA = OPA == OP_N ? NTHR / MT : NTHR / KT;
+  constexpr int DB = OPB == OP_N ? NTHR / KT : NTHR / NT;
+  const int a_fast = OPA == OP_N ? tid % MT : tid % KT;  // contiguous direction in storage
+  const int a_slow = OPA == OP_N ? tid / MT : tid / KT;
+  const int b_fast = OPB == OP_N ? tid % KT : tid % NT;
+  const int b_slow = OPB == OP_N ? tid / KT : tid / NT;
+
+  double ra_re[LA], ra_im[LA], rb_re[LB], rb_im[LB];
 
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int m, k;
-      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
+    for (int i = 0; i < LA; ++i) {
+      const int m = OPA == OP_N ? a_fast : a_slow + DA * i;
+      const int k = OPA == OP_N ? a_slow + DA * i : a_fast;
       const int gm = m0 + m, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if (gm < g.M && gk < kend) {
+      if (!EDGE || (gm < g.M && gk < kend)) {
+        cplx v;
         if (OPA == OP_N) {
-          const long row = g.idxA ? g.idxA[gm] : gm;
-          const cplx v = A[row + (long)gk * g.lda];
-          re = v.re; im = v.im;
+          const long row = GATHER && g.idxA ? g.idxA[gm] : gm;
+          v = A[row + (long)gk * g.lda];
         } else {
-          const long row = g.idxA ? g.idxA[gk] : gk;
-          const cplx v = A[row + (long)gm * g.lda];
-          re = v.re; im = -v.im;
+          const long row = GATHER && g.idxA ? g.idxA[gk] : gk;
+          v = A[row + (long)gm * g.lda];
+          v.im = -v.im;
         }
+        re = v.re; im = v.im;
       }
       ra_re[i] = re; ra_im[i] = im;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int n, k;
-      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * i; }
-      else { n = tid & 63; k = (tid >> 6) + 4 * i; }
+    for (int i = 0; i < LB; ++i) {
+      const int n = OPB == OP_N ? b_slow + DB * i : b_fast;
+      const int k = OPB == OP_N ? b_fast : b_slow + DB * i;
       const int gn = n0 + n, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if (gn < g.N && gk < kend) {
+      if (!EDGE || (gn < g.N && gk < kend)) {
+        cplx v;
         if (OPB == OP_N) {
-          const long row = g.idxB ? g.idxB[gk] : gk;
-          const cplx v = B[row + (long)gn * g.ldb];
-          re = v.re; im = v.im;
+          const long row = GATHER && g.idxB ? g.idxB[gk] : gk;
+          v = B[row + (long)gn * g.ldb];
         } else {
-          const long row = g.idxB ? g.idxB[gn] : gn;
-          const cplx v = B[row + (long)gk * g.ldb];
-          re = v.re; im = -v.im;
+          const long row = GATHER && g.idxB ? g.idxB[gn] : gn;
+          v = B[row + (long)gk * g.ldb];
+          v.im = -v.im;
         }
+        re = v.re; im = v.im;
       }
       rb_re[i] = re; rb_im[i] = im;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int m, k;
-      if (OPA == OP_N) { m = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
+    for (int i = 0; i < LA; ++i) {
+      const int m = OPA == OP_N ? a_fast : a_slow + DA * i;
+      const int k = OPA == OP_N ? a_slow + DA * i : a_fast;
       Ar[buf][k][m] = ra_re[i];
       Ai[buf][k][m] = ra_im[i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int n, k;
-      if (OPB == OP_N) { k = tid & 15; n = (tid >> 4) + 16 * i; }
-      else { n = tid & 63; k = (tid >> 6) + 4 * i; }
+    for (int i = 0; i < LB; ++i) {
+      const int n = OPB == OP_N ? b_slow + DB * i : b_fast;
+      const int k = OPB == OP_N ? b_fast : b_slow + DB * i;
       Br[buf][k][n] = rb_re[i];
       Bi[buf][k][n] = rb_im[i];
     }
   };
 
-  d4 acc_re[2][2], acc_im[2][2];
+  d4 acc_re[IM][JN], acc_im[IM][JN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < JN; ++j) {
       acc_re[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       acc_im[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
@@ -131,34 +204,35 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       const int k = kk + (lane >> 4);
-      double a_re[2], a_im[2], a_nim[2], b_re[2], b_im[2];
+      double a_re[IM], a_im[IM], b_re[JN], b_im[JN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int row = wr * 32 + i * 16 + (lane & 15);
+      for (int i = 0; i < IM; ++i) {
+        const int row = wr * (MT / WM) + i * 16 + (lane & 15);
         a_re[i] = Ar[buf][k][row];
         a_im[i] = Ai[buf][k][row];
-        a_nim[i] = -a_im[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int col = wc * 32 + j * 16 + (lane & 15);
+      for (int j = 0; j < JN; ++j) {
+        const int col = wc * (NT / WN) + j * 16 + (lane & 15);
         b_re[j] = Br[buf][k][col];
         b_im[j] = Bi[buf][k][col];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < JN; ++j) {
           acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_re[i], b_re[j], acc_re[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_re[i], b_im[j], acc_im[i][j], 0, 0, 0);
         }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i) {
+        const double a_nim = -a_im[i];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_nim[i], b_im[j], acc_re[i][j], 0, 0, 0);
+        for (int j = 0; j < JN; ++j) {
+          acc_re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_nim, b_im[j], acc_re[i][j], 0, 0, 0);
           acc_im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_im[i], b_re[j], acc_im[i][j], 0, 0, 0);
         }
+      }
     }
     if (it + 1 < nk) store(buf ^ 1);
     __syncthreads();
@@ -169,14 +243,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
   const cplx *Cin = g.Cin ? g.Cin + (long)b * g.sCin : nullptr;
   cplx *D = g.D + (long)b * g.sD;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr * 32 + i * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + wc * 32 + j * 16 + (lane & 15);
-        if (row >= g.M || col >= g.N) continue;
+        const int row = m0 + wr * (MT / WM) + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wc * (NT / WN) + j * 16 + (lane & 15);
+        if (EDGE && (row >= g.M || col >= g.N)) continue;
         if (g.tri == TRI_UPPER && row > col) continue;
         const double xr = acc_re[i][j][r], xi = acc_im[i][j][r];
         double yr = g.alpha.re * xr - g.alpha.im * xi;
@@ -190,17 +264,75 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc g) {
       }
 }
 
+template <int MT>
+constexpr int kchunk() { return 16; }
+template <int NT>
+constexpr int nthreads() { return 64 * 2 * (NT / 32); }
+
+template <int OPA, int OPB, int MT, int NT, bool GATHER, bool EDGE>
+__global__ __launch_bounds__(nthreads<NT>()) void zgemm_kernel(GemmDesc g) {
+  zgemm_body<OPA, OPB, MT, NT, kchunk<MT>(), GATHER, EDGE>(g);
+}
+
+// The propagator product U <- P U gets its own symbol so that profilers can
+// tell it apart from the other contractions of a step.
+template <bool EDGE>
+__global__ __launch_bounds__(512) void propagator_zgemm_kernel(GemmDesc g) {
+  zgemm_body<OP_N, OP_N, 128, 128, kchunk<128>(), false, EDGE>(g);
+}
+
+template <int MT, int NT>
+unsigned grid_size(const GemmDesc &g) {
+  const TileMap t = make_map(g.M, g.N, g.batch, MT, NT, g.tri);
+  if (t.linear) return (unsigned)((long)t.groups * t.per_group);
+  const long groups_per_xcd = (t.groups + NXCD - 1) / NXCD;
+  return (unsigned)(groups_per_xcd * NXCD * t.per_group);
+}
+
+template <int MT, int NT>
+bool needs_edge(const GemmDesc &g) {
+  constexpr int KT = kchunk<MT>();
+  return (g.M % MT) || (g.N % NT) || (g.K % KT);
+}
+
+template <int MT, int NT, bool GATHER, bool EDGE>
+void launch_ops(const GemmDesc &g, dim3 grid, hipStream_t s) {
+  const dim3 block(nthreads<NT>());
+  if (g.opA == OP_N && g.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+  else if (g.opA == OP_C && g.opB == OP_N)
+    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+  else if (g.opA == OP_N && g.opB == OP_C)
+    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_C, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+}
+
+template <int MT, int NT>
+hipError_t launch(const GemmDesc &g, hipStream_t s) {
+  const dim3 grid(grid_size<MT, NT>(g));
+  if (g.idxA || g.idxB) launch_ops<MT, NT, true, true>(g, grid, s);
+  else if (needs_edge<MT, NT>(g)) launch_ops<MT, NT, false, true>(g, grid, s);
+  else launch_ops<MT, NT, false, false>(g, grid, s);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  const dim3 grid(grid_size<128, 128>(g));
+  if (needs_edge<128, 128>(g)) hipLaunchKernelGGL(propagator_zgemm_kernel<true>, grid, dim3(512), 0, s, g);
+  else hipLaunchKernelGGL(propagator_zgemm_kernel<false>, grid, dim3(512), 0, s, g);
+  return hipGetLastError();
+}
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  dim3 grid((g.M + MT - 1) / MT, (g.N + NT - 1) / NT, g.batch);
-  dim3 block(256);
-  if (g.opA == OP_N && g.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N>), grid, block, 0, s, g);
-  else if (g.opA == OP_C && g.opB == OP_N) hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N>), grid, block, 0, s, g);
-  else if (g.opA == OP_N && g.opB == OP_C) hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C>), grid, block, 0, s, g);
-  else hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_C>), grid, block, 0, s, g);
-  return hipGetLastError();
+  // Large tiles only when every dimension fills them and there is enough work.
+  const long work = (long)g.M * g.N * g.batch;
+  if (g.M >= 128 && g.N >= 128 && g.K >= 128 && work >= (1L << 22)) return launch<128, 128>(g, s);
+  return launch<64, 64>(g, s);
 }
 
 }  // namespace mfq

@@ -15,6 +15,7 @@ import numpy as np
 PROJECTIVE = 0
 HOMODYNE = 1
 FP64 = 0
+FP32_BULK = 1
 
 MFQ_OK = 0
 _ERRORS = {-1: "MFQ_EINVAL", -2: "MFQ_ENOMEM", -3: "MFQ_EDEVICE", -4: "MFQ_ENUMERIC", -5: "MFQ_ESTATE"}
@@ -57,7 +58,11 @@ _SIGS = {
     "mfq_get_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mfq_set_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "mfq_synchronize": (ctypes.c_int32, [ctypes.c_void_p]),
+    "mfq_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_phase_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
+
+PHASES = ("propagate", "measure", "reorth", "observe")
 
 EXPORTED = tuple(_SIGS)
 
@@ -176,6 +181,17 @@ def mfq_synchronize(ctx):
     _check(ctx, lib().mfq_synchronize(ctx))
 
 
+def mfq_profile(ctx, enable):
+    _check(ctx, lib().mfq_profile(ctx, 1 if enable else 0))
+
+
+def mfq_phase_times(ctx):
+    ms = np.zeros(len(PHASES))
+    cnt = np.zeros(len(PHASES), dtype=np.int64)
+    _check(ctx, lib().mfq_phase_times(ctx, _ptr(ms), _ptr(cnt)))
+    return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(PHASES)}
+
+
 # ------------------------------------------------------------------ convenience object
 
 class Trajectories:
@@ -184,7 +200,8 @@ class Trajectories:
     The workspace is a PyTorch CUDA tensor; work runs on PyTorch's current stream.
     """
 
-    def __init__(self, dim, Lx, Ly=1, N=None, n_traj=1, uids=None, occupied=None, J=1.0, device=0):
+    def __init__(self, dim, Lx, Ly=1, N=None, n_traj=1, uids=None, occupied=None, J=1.0, device=0,
+                 precision=FP64):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libmfq runs only on the GPU")
@@ -198,9 +215,9 @@ class Trajectories:
         torch.cuda.set_device(device)
         self.stream = torch.cuda.current_stream(device)
         self.ctx = mfq_create(device, ctypes.c_void_p(self.stream.cuda_stream))
-        nb = mfq_workspace_bytes(self.lat, self.N, n_traj)
+        nb = mfq_workspace_bytes(self.lat, self.N, n_traj, precision)
         self.ws = torch.empty(nb, dtype=torch.uint8, device=f"cuda:{device}")
-        mfq_init_state(self.ctx, self.lat, self.N, n_traj, self.uids, occupied, FP64,
+        mfq_init_state(self.ctx, self.lat, self.N, n_traj, self.uids, occupied, precision,
                        ctypes.c_void_p(self.ws.data_ptr()), nb)
 
     def step(self, protocol, gamma, dt, seed, n_steps=1):
@@ -230,6 +247,12 @@ class Trajectories:
 
     def synchronize(self):
         mfq_synchronize(self.ctx)
+
+    def profile(self, enable=True):
+        mfq_profile(self.ctx, enable)
+
+    def phase_times(self):
+        return mfq_phase_times(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

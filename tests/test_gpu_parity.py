@@ -223,3 +223,22 @@ def test_batched_homodyne_ring_full_size_sampled():
     for t in sample:
         assert np.abs(corr(U[t]) - corr(ob.U[t])).max() < 1e-10
     sim.close()
+
+
+def test_strong_homodyne_uses_full_second_pass():
+    """gamma*dt = 2: factors up to e^{+-6} make U far from orthonormal before the first
+    Cholesky-QR pass, so the second pass fails the near-identity test and runs the full
+    factorisation on the device; results still match the oracle's Householder QR."""
+    L, B = 64, 4
+    sim = make_sim(1, L, n_traj=B, uids=range(B))
+    ob = OracleBatch(1, L, 1, 0.05, range(B))
+    for n in range(6):
+        sim.step(QSD, [40.0] * B, 0.05, 8)
+        ob.step(QSD, [40.0] * B, 8)
+    S = sim.entropy(list(range(32)))
+    assert np.abs(S - ob.entropy(list(range(32)))).max() <= 1e-8
+    U, _ = sim.get_state()
+    for t in range(B):
+        assert np.abs(np.conj(U[t].T) @ U[t] - np.eye(32)).max() < 1e-12
+        assert np.abs(corr(U[t]) - corr(ob.U[t])).max() < 1e-9
+    sim.close()
