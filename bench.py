@@ -22,7 +22,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 1 << 30      # calibration copy for the HBM byte counters
 PMC_FILE = os.path.join(ROOT, "profiles", "propagator_zgemm_ring1024_qsd_pmc.json")
 GEMM_SRC = os.path.join(ROOT, "paper_2508_18468_amd", "csrc", "zgemm.hip")
 
@@ -75,6 +77,66 @@ def cpu_baseline(w, steps):
                       f"{dt:.1f} s wall"}
 
 
+def pmc_workload():
+    """Short run for hardware-counter passes: 3 FP64 steps of the benchmark workload, then a
+    plain device-to-device copy of COPY_BYTES (the calibration kernel for FETCH/WRITE_SIZE)."""
+    import numpy as np
+    import torch
+    from paper_2508_18468_amd import mfq
+    from paper_2508_18468_amd.workloads import ring_qsd_batched
+    w = ring_qsd_batched()
+    uids = w.uids(0) + w.uids(1) + w.uids(2)
+    gam = np.repeat(np.asarray(w.gammas), w.n_traj)
+    sim = mfq.Trajectories(1, w.Lx, n_traj=len(uids), uids=uids, device=0)
+    sim.step(mfq.HOMODYNE, gam, w.dt, w.seed, 3)
+    sim.synchronize()
+    sim.close()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 2.0, out=dst)  # elementwise kernel: reads COPY_BYTES, writes COPY_BYTES
+    torch.cuda.synchronize()
+    print("pmc workload done")
+
+
+def _pmc_rows(path):
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        val = float(r.get("Counter_Value", "nan"))
+        out.append((int(r.get("Dispatch_Id", 0)), name, r.get("Counter_Name", ""), val))
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv, out_path):
+    """Per-launch HBM bytes of the propagator kernel from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for the calibration copy of known size."""
+    res = {}
+    for label, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _pmc_rows(path)
+        prop = [v for (_, n, c, v) in rows if "propagator_zgemm_kernel" in n]
+        # the calibration kernel is the multiply (the fill before it reads nothing)
+        copy = [v for (_, n, c, v) in rows if "elementwise" in n and "Mul" in n]
+        copy_kib = copy[-1] if copy else None
+        scale = COPY_BYTES / (copy_kib * 1024.0) if copy_kib else None
+        res[label] = {"propagator_kib_per_dispatch": prop, "copy_kib": copy_kib, "scale": scale}
+    f = res["fetch"]; wr = res["write"]
+    per_launch = None
+    if f["propagator_kib_per_dispatch"] and wr["propagator_kib_per_dispatch"] and f["scale"] and wr["scale"]:
+        fk = sum(f["propagator_kib_per_dispatch"]) / len(f["propagator_kib_per_dispatch"])
+        wk = sum(wr["propagator_kib_per_dispatch"]) / len(wr["propagator_kib_per_dispatch"])
+        per_launch = fk * 1024.0 * f["scale"] + wk * 1024.0 * wr["scale"]
+    d = {"kernel": "propagator_zgemm_kernel", "workload": "ring1024_qsd", "n_traj": 384,
+         "kernel_source_sha256": source_hash(), "copy_bytes": COPY_BYTES,
+         "fetch": res["fetch"], "write": res["write"], "hbm_bytes_per_launch": per_launch,
+         "algorithmic_bytes_per_launch": 16.0 * (1024 * 1024 + 2 * 1024 * 512 * 384)}
+    with open(out_path, "w") as fo:
+        json.dump(d, fo, indent=1)
+    print(json.dumps(d))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +144,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="short run for rocprofv3 --pmc passes (3 steps + calibration copy)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    if args.pmc_workload:
+        pmc_workload()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: trajectories shard across GPUs with no communication, "
               "so the multi-GPU figure is n_gpus x the one-GPU value; --gpus must be 1", file=sys.stderr)
@@ -98,44 +169,55 @@ def main():
     B = len(uids)
     gam = np.repeat(np.asarray(w.gammas), w.n_traj)
     region = w.regions[0]
-    sim = mfq.Trajectories(1, w.Lx, n_traj=B, uids=uids, device=0)
-
-    def advance(n_steps, observe):
-        """Advance n_steps, observing S whenever the absolute step hits the schedule."""
-        done = 0
-        n_obs = 0
-        while done < n_steps:
-            cur = sim_step[0]
-            to_obs = w.obs_every - (cur % w.obs_every)
-            chunk = min(n_steps - done, to_obs)
-            sim.step(mfq.HOMODYNE, gam, w.dt, w.seed, chunk)
-            sim_step[0] += chunk
-            done += chunk
-            if observe and sim_step[0] % w.obs_every == 0:
-                sim.entropy(region)
-                n_obs += 1
-        return n_obs
-
-    sim_step = [0]
-    advance(args.warmup, observe=True)
-    torch.cuda.synchronize()
-    sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n_obs = advance(args.steps, observe=True)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    phases = sim.phase_times()
-    sim.profile(False)
-    T = t1 - t0
-
     L, N = w.L, w.N
-    value = B * L * N * args.steps / T
-    prop_ms, prop_n = phases["propagate"]
-    gemm_flops = 8.0 * L * L * N * B
-    gemm_tflops = gemm_flops / (prop_ms / prop_n * 1e-3) / 1e12 if prop_n else None
+
+    def run_path(precision):
+        """Warm up, then time `steps` steps (entropy inside the window on schedule)."""
+        sim = mfq.Trajectories(1, w.Lx, n_traj=B, uids=uids, device=0, precision=precision)
+        state = {"step": 0, "S": None}
+
+        def advance(n_steps):
+            done = n_obs = 0
+            while done < n_steps:
+                chunk = min(n_steps - done, w.obs_every - (state["step"] % w.obs_every))
+                sim.step(mfq.HOMODYNE, gam, w.dt, w.seed, chunk)
+                state["step"] += chunk
+                done += chunk
+                if state["step"] % w.obs_every == 0:
+                    state["S"] = (state["step"], sim.entropy(region))
+                    n_obs += 1
+            return n_obs
+
+        advance(args.warmup)
+        torch.cuda.synchronize()
+        sim.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_obs = advance(args.steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        phases = sim.phase_times()
+        sim.profile(False)
+        sim.close()
+        prop_ms, prop_n = phases["propagate"]
+        gemm_flops = 8.0 * L * L * N * B
+        return {"T": T, "n_obs": n_obs, "phases": phases, "S": state["S"],
+                "value": B * L * N * args.steps / T,
+                "prop_ms": prop_ms / prop_n if prop_n else None,
+                "gemm_tflops": gemm_flops / (prop_ms / prop_n * 1e-3) / 1e12 if prop_n else None,
+                "gemm_flops": gemm_flops}
+
+    r64 = run_path(mfq.FP64)
+    r32 = run_path(mfq.FP32_BULK)
+    T = r64["T"]
+    value = r64["value"]
+    gemm_tflops = r64["gemm_tflops"]
     traffic = traffic_from_profile(B)
+    rel_dS = None
+    if r64["S"] and r32["S"] and r64["S"][0] == r32["S"][0]:
+        S64, S32 = r64["S"][1], r32["S"][1]
+        rel_dS = float(np.max(np.abs(S32 - S64) / np.abs(S64)))
     out = {
         "metric": "L*N*steps/s",
         "value": value,
@@ -153,21 +235,29 @@ def main():
                                "{0.1,0.3,1.0} x 128 trajectories batched, dt=0.05, S of A=[0,512) "
                                "every 100 steps",
                    "L": L, "N": N, "n_traj": B, "dt": w.dt, "obs_every": w.obs_every,
-                   "observations_timed": n_obs, "precision": "fp64"},
+                   "observations_timed": r64["n_obs"], "precision": "fp64"},
         "gemm_tflops": gemm_tflops,
         "roofline": {"bound": "mfma", "achieved": gemm_tflops, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": (gemm_tflops / PEAK_FP64_TFLOPS) if gemm_tflops else None,
                      "traffic": traffic, "kernel": "propagator_zgemm_kernel",
-                     "algorithmic_flops_per_launch": gemm_flops,
-                     "avg_launch_ms": prop_ms / prop_n if prop_n else None},
-        "phase_ms_per_step": {k: (v[0] / args.steps) for k, v in phases.items()},
+                     "algorithmic_flops_per_launch": r64["gemm_flops"],
+                     "avg_launch_ms": r64["prop_ms"]},
+        "phase_ms_per_step": {k: (v[0] / args.steps) for k, v in r64["phases"].items()},
+        "fp32_bulk": {"value": r32["value"], "unit": "L*N*steps/s",
+                      "ms_per_step": r32["T"] / args.steps * 1e3,
+                      "speedup_vs_fp64": r32["value"] / value,
+                      "propagator_tflops": r32["gemm_tflops"],
+                      "propagator_frac_of_fp32_mfma_peak": (r32["gemm_tflops"] / PEAK_FP32_TFLOPS
+                                                            if r32["gemm_tflops"] else None),
+                      "phase_ms_per_step": {k: (v[0] / args.steps) for k, v in r32["phases"].items()},
+                      "max_rel_dS_vs_fp64": rel_dS,
+                      "rel_dS_at_step": r64["S"][0] if r64["S"] else None},
         "traj_latency_s": {"p50": None, "p99": None,
                            "note": "all 384 trajectories of the batch complete together; "
                                    "2000-step run extrapolated below"},
         "traj_run_s_extrapolated_2000_steps": T / args.steps * w.n_steps,
     }
     out["traj_latency_s"]["p50"] = out["traj_latency_s"]["p99"] = out["traj_run_s_extrapolated_2000_steps"]
-    sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out))

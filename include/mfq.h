@@ -161,6 +161,11 @@ mfq_status mfq_set_state(mfq_ctx *ctx, const void *U_host, int64_t step);
  * (MFQ_ENUMERIC) and clears them. */
 mfq_status mfq_synchronize(mfq_ctx *ctx);
 
+/* Multi-step calls (n_steps >= 2) replay a captured HIP graph of two steps
+ * (default on; off while phase timing is enabled).  enable = 0 launches every
+ * kernel directly.  Results are identical either way. */
+mfq_status mfq_use_graphs(mfq_ctx *ctx, int32_t enable);
+
 /* Phase timing with HIP events recorded on the context's stream around each
  * phase of a step (no extra synchronisation while enabled). */
 #define MFQ_PHASE_PROPAGATE 0 /* propagator GEMM U <- P U: exactly one kernel launch per step */

@@ -49,6 +49,14 @@ struct mfq_ctx {
   std::vector<int> rec_phase;         // interval i: phase, events 2i and 2i+1
   double phase_ms[MFQ_NPHASES] = {0, 0, 0, 0};
   int64_t phase_n[MFQ_NPHASES] = {0, 0, 0, 0};
+  // step counter on the device and the cached two-step graph
+  int64_t *step_dev = nullptr;
+  bool use_graphs = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_protocol = -1, g_cur = -1;
+  double g_dt = NAN;
+  uint64_t g_seed = 0;
 };
 
 namespace {
@@ -127,6 +135,7 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   c->Pr32 = pr32; c->Pi32 = pi32;
   c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy;
   c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
+  c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
   c->eig = EigWork{G, ev, ew, ed, ee, elam, eS};
   c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
   c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
@@ -277,6 +286,82 @@ mfq_status entropy_dev(mfq_ctx *c, const int32_t *region, int32_t n, double *S_h
   return MFQ_OK;
 }
 
+
+// Enqueue one step on the stream (state X[cur] -> X[1-cur]); the step index is
+// read on the device as *step_dev + step_offset.
+mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int step_offset) {
+  const int L = c->L, N = c->N, B = c->B;
+  cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
+  // propagator: Xb = P Xa, the batch as one L x (N*B) matrix
+  GemmDesc g{};
+  g.M = L; g.N = N * B; g.K = L; g.batch = 1;
+  g.A = c->P; g.lda = L; g.opA = OP_N;
+  g.B = Xa; g.ldb = L; g.opB = OP_N;
+  g.D = Xb; g.ldd = L;
+  g.alpha = cplx{1.0, 0.0};
+  {
+    PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
+    if (c->precision == MFQ_FP32_BULK)
+      HIPCHK(propagator_delta_f32(c->Pr32, c->Pi32, Xa, Xb, L, N * B, c->stream), "propagator f32");
+    else
+      HIPCHK(zgemm_propagator(g, c->stream), "propagator gemm");
+  }
+  {
+    PhaseTimer t(c, MFQ_PHASE_MEASURE);
+    if (protocol == MFQ_HOMODYNE) {
+      HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
+                           c->stream), "homodyne");
+    } else {
+      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset, c->pm_sites,
+                        c->pm_out, c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
+    }
+  }
+  {
+    PhaseTimer t(c, MFQ_PHASE_REORTH);
+    HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, false, c->stream), "cholqr pass 1");
+    HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, true, c->stream), "cholqr pass 2");
+  }
+  c->cur = 1 - c->cur;
+  return MFQ_OK;
+}
+
+void drop_graph(mfq_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
+// A graph of two consecutive steps (so the state returns to the same buffer)
+// plus the step-counter advance; rebuilt when protocol, dt, seed or buffer
+// parity change.  Replayed with hipGraphLaunch for each pair of steps.
+mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed) {
+  if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur)
+    return MFQ_OK;
+  drop_graph(c);
+  const int cur0 = c->cur;
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "begin capture");
+  mfq_status st = enqueue_step(c, protocol, dt, seed, 1);
+  if (!st) st = enqueue_step(c, protocol, dt, seed, 2);
+  hipError_t e = st ? hipSuccess : set_step(c->step_dev, 2, true, c->stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+  c->cur = cur0;
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "capture");
+  if (e2 != hipSuccess) return hip_fail(c, e2, "end capture");
+  c->graph = graph;
+  HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0), "graph instantiate");
+  c->g_protocol = protocol;
+  c->g_dt = dt;
+  c->g_seed = seed;
+  c->g_cur = cur0;
+  return MFQ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -311,6 +396,7 @@ mfq_status mfq_destroy(mfq_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  drop_graph(c);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -386,6 +472,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
     c->own_ws = true;
     c->ws_bytes = need;
   }
+  drop_graph(c);
   Plan pl;
   pl.base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws)));
   carve(pl, L, N, n_traj, precision, c);
@@ -426,41 +513,26 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     HIPCHK(hipMemcpyAsync(c->gamma, c->gamma_host.data(), c->B * sizeof(double), hipMemcpyHostToDevice,
                           c->stream), "gamma upload");
   }
-  const int L = c->L, N = c->N, B = c->B;
-  for (int s = 0; s < n_steps; ++s) {
-    const int64_t n = c->step + 1;
-    cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
-    // propagator: Xb = P Xa, the batch as one L x (N*B) matrix
-    GemmDesc g{};
-    g.M = L; g.N = N * B; g.K = L; g.batch = 1;
-    g.A = c->P; g.lda = L; g.opA = OP_N;
-    g.B = Xa; g.ldb = L; g.opB = OP_N;
-    g.D = Xb; g.ldd = L;
-    g.alpha = cplx{1.0, 0.0};
-    {
-      PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
-      if (c->precision == MFQ_FP32_BULK)
-        HIPCHK(propagator_delta_f32(c->Pr32, c->Pi32, Xa, Xb, L, N * B, c->stream), "propagator f32");
-      else
-        HIPCHK(zgemm_propagator(g, c->stream), "propagator gemm");
-    }
-    {
-      PhaseTimer t(c, MFQ_PHASE_MEASURE);
-      if (protocol == MFQ_HOMODYNE) {
-        HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, n, c->stream), "homodyne");
-      } else {
-        HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, n, c->pm_sites, c->pm_out,
-                          c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
-      }
-    }
-    {
-      PhaseTimer t(c, MFQ_PHASE_REORTH);
-      HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, false, c->stream), "cholqr pass 1");
-      HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, true, c->stream), "cholqr pass 2");
-    }
-    c->cur = 1 - c->cur;
-    c->step = n;
+  HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
+  int done = 0;
+  if (c->use_graphs && !c->profiling && n_steps >= 2) {
+    mfq_status st = ensure_step_graph(c, protocol, dt, seed);
+    if (st) return st;
+    for (; done + 2 <= n_steps; done += 2) HIPCHK(hipGraphLaunch(c->gexec, c->stream), "graph launch");
   }
+  for (; done < n_steps; ++done) {
+    mfq_status st = enqueue_step(c, protocol, dt, seed, 1);
+    if (st) return st;
+    HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
+  }
+  c->step += n_steps;
+  return MFQ_OK;
+}
+
+mfq_status mfq_use_graphs(mfq_ctx *c, int32_t enable) {
+  if (!c) return MFQ_EINVAL;
+  c->use_graphs = enable != 0;
+  if (!c->use_graphs) drop_graph(c);
   return MFQ_OK;
 }
 

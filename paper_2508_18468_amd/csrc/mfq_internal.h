@@ -47,12 +47,16 @@ hipError_t propagator_delta_f32(const float *Pr, const float *Pi, const cplx *U,
 hipError_t expand_propagator(cplx *P, const cplx *gx, const cplx *gy, int dim, int Lx, int Ly,
                              hipStream_t s);
 hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t s);
+// The absolute step index n of a step is read on the device as *step_ptr + step_offset,
+// so that a captured graph of steps can be replayed unchanged.
+hipError_t set_step(int64_t *step_ptr, int64_t value, bool add, hipStream_t s);
 hipError_t born_homodyne(cplx *U, double *p, int L, int N, int B, const double *gamma, double dt,
-                         uint64_t seed, const uint64_t *uid, int64_t step, hipStream_t s);
+                         uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
+                         hipStream_t s);
 hipError_t born_only(const cplx *U, double *p, int L, int N, int B, hipStream_t s);
 hipError_t pm_measure(cplx *U, int L, int N, int B, const double *gamma, double dt, uint64_t seed,
-                      const uint64_t *uid, int64_t step, int *sites, int *outcomes, double *probs,
-                      int *counts, cplx *vbuf, cplx *wbuf, hipStream_t s);
+                      const uint64_t *uid, const int64_t *step_ptr, int step_offset, int *sites,
+                      int *outcomes, double *probs, int *counts, cplx *vbuf, cplx *wbuf, hipStream_t s);
 hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- Cholesky-QR

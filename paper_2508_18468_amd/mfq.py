@@ -59,6 +59,7 @@ _SIGS = {
     "mfq_set_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "mfq_synchronize": (ctypes.c_int32, [ctypes.c_void_p]),
     "mfq_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_use_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_phase_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
@@ -181,6 +182,10 @@ def mfq_synchronize(ctx):
     _check(ctx, lib().mfq_synchronize(ctx))
 
 
+def mfq_use_graphs(ctx, enable):
+    _check(ctx, lib().mfq_use_graphs(ctx, 1 if enable else 0))
+
+
 def mfq_profile(ctx, enable):
     _check(ctx, lib().mfq_profile(ctx, 1 if enable else 0))
 
@@ -247,6 +252,9 @@ class Trajectories:
 
     def synchronize(self):
         mfq_synchronize(self.ctx)
+
+    def use_graphs(self, enable=True):
+        mfq_use_graphs(self.ctx, enable)
 
     def profile(self, enable=True):
         mfq_profile(self.ctx, enable)
