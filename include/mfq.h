@@ -53,6 +53,7 @@ typedef int32_t mfq_status;
 #define MFQ_EDEVICE (-3)  /* HIP runtime error */
 #define MFQ_ENUMERIC (-4) /* Cholesky breakdown or a non-finite value */
 #define MFQ_ESTATE (-5)   /* call out of order (e.g. step before init_state) */
+#define MFQ_PENDING 1     /* serving engine: job not finished yet */
 
 #define MFQ_PROJECTIVE 0  /* projective n_i measurements, Appendix A (PM) */
 #define MFQ_HOMODYNE 1    /* homodyne / quantum state diffusion, Eq. (A4) (QSD) */
@@ -161,6 +162,31 @@ mfq_status mfq_set_state(mfq_ctx *ctx, const void *U_host, int64_t step);
  * (MFQ_ENUMERIC) and clears them. */
 mfq_status mfq_synchronize(mfq_ctx *ctx);
 
+/* Run n_steps steps (as mfq_step) and record S_A of one region after every
+ * step whose absolute index is a multiple of obs_every (0: no observation).
+ * S_host receives n_obs x n_traj doubles, observation-major, where *n_obs_out
+ * = number of such steps in the run.  Execution path (mfq_set_path): on the
+ * fused path one workgroup per trajectory runs every step and observation
+ * with its state in LDS, in a single launch (lattices whose state, Gram and
+ * factor fit in a compute unit's LDS, e.g. L = 64); otherwise the per-phase
+ * kernels run (graph-replayed) with the entropy pipeline on schedule.  Both
+ * paths use the same random numbers.  Synchronises. */
+mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                   int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
+                   double *S_host, int32_t *n_obs_out);
+
+#define MFQ_PATH_AUTO 0     /* fused when the problem fits in LDS, else per-phase kernels */
+#define MFQ_PATH_FUSED 1    /* force the fused single-launch path (MFQ_EINVAL if it does not fit) */
+#define MFQ_PATH_LAUNCHES 2 /* force the per-phase kernels */
+mfq_status mfq_set_path(mfq_ctx *ctx, int32_t path);
+
+/* Continuous batching: put trajectory `slot` back into the initial state of
+ * mfq_init_state with a new uid, without touching the other trajectories.
+ * Its own step index restarts at 0 (its random numbers are those of a fresh
+ * trajectory with this uid: counter step = context step - step at reset).
+ * Stream-ordered, asynchronous. */
+mfq_status mfq_reset_trajectory(mfq_ctx *ctx, int32_t slot, uint64_t uid);
+
 /* Multi-step calls (n_steps >= 2) replay a captured HIP graph of two steps
  * (default on; off while phase timing is enabled).  enable = 0 launches every
  * kernel directly.  Results are identical either way. */
@@ -181,6 +207,62 @@ mfq_status mfq_profile(mfq_ctx *ctx, int32_t enable);
  * timing was enabled; ms and count are host arrays of MFQ_NPHASES entries
  * (either may be NULL).  Synchronises. */
 mfq_status mfq_phase_times(mfq_ctx *ctx, double *ms, int64_t *count);
+
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of trajectory jobs of different
+ * lattices, sizes and protocols on one device.  A worker thread admits queued
+ * jobs into batch groups (one context per shape = lattice, N, protocol,
+ * precision, dt, seed) by device-memory footprint, refills slots as jobs
+ * finish while the other slots keep running, and runs the groups' steps on
+ * separate streams so that they overlap on the device.  Every job starts
+ * from the Neel / checkerboard state (N = L/2) and keeps its own random
+ * numbers (key (seed, uid), counter = its own step index), so its result is
+ * the same alone and in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct mfq_engine mfq_engine;
+
+typedef struct {
+  mfq_lattice lat;
+  int32_t N;          /* 0 or L/2 */
+  int32_t protocol;   /* MFQ_PROJECTIVE or MFQ_HOMODYNE */
+  int32_t precision;  /* MFQ_FP64 or MFQ_FP32_BULK */
+  int32_t n_steps;    /* >= 1 */
+  int32_t obs_every;  /* S of `region` after every obs_every-th step of the job; 0: after the last */
+  int32_t n_region;
+  double gamma;       /* monitoring rate, >= 0 */
+  double dt;          /* > 0 */
+  uint64_t seed;
+  uint64_t uid;       /* keys the job's random numbers */
+  const int32_t *region;  /* n_region ascending site ids, copied at submission */
+} mfq_job;
+
+typedef struct {
+  uint64_t bytes_in_use;  /* device memory held by the engine's batch groups */
+  uint64_t peak_bytes;
+  uint64_t budget_bytes;
+  int64_t queued;         /* jobs waiting for a slot or for memory */
+  int32_t groups;         /* live batch groups */
+  int32_t reserved;
+} mfq_engine_stats_t;
+
+/* Start an engine on `device` that keeps at most hbm_budget_bytes of device
+ * workspace (0: 64 GiB) and at most max_slots trajectories per batch group. */
+mfq_status mfq_engine_create(int device, size_t hbm_budget_bytes, int32_t max_slots, mfq_engine **out);
+/* Stop the worker (running jobs are abandoned) and free everything. */
+mfq_status mfq_engine_destroy(mfq_engine *engine);
+const char *mfq_engine_last_error(const mfq_engine *engine);
+/* Queue a job (non-blocking); *job_id identifies it.  A job whose footprint
+ * alone exceeds the budget fails (poll returns MFQ_ENOMEM). */
+mfq_status mfq_engine_submit(mfq_engine *engine, const mfq_job *job, uint64_t *job_id);
+/* MFQ_PENDING (1) until the job is done; then copies up to max_obs entropies
+ * (in order of observation) to S_host, their number to *n_obs and the time
+ * from submission to completion to *latency_s (any output may be NULL). */
+mfq_status mfq_engine_poll(mfq_engine *engine, uint64_t job_id, double *S_host, int32_t max_obs,
+                           int32_t *n_obs, double *latency_s);
+/* Block until the job is done (MFQ_OK), failed (its error) or timeout_s
+ * elapsed (MFQ_PENDING). */
+mfq_status mfq_engine_wait(mfq_engine *engine, uint64_t job_id, double timeout_s);
+mfq_status mfq_engine_stats(mfq_engine *engine, mfq_engine_stats_t *out);
 
 #ifdef __cplusplus
 }

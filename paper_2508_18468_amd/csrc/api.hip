@@ -51,12 +51,17 @@ struct mfq_ctx {
   int64_t phase_n[MFQ_NPHASES] = {0, 0, 0, 0};
   // step counter on the device and the cached two-step graph
   int64_t *step_dev = nullptr;
+  int64_t *step_base = nullptr;  // per trajectory: own step = step - step_base[b]
   bool use_graphs = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_protocol = -1, g_cur = -1;
   double g_dt = NAN;
   uint64_t g_seed = 0;
+  // mfq_run: execution path and its observation buffer
+  int run_path = 0;  // MFQ_PATH_AUTO
+  double *run_S = nullptr;
+  size_t run_S_cap = 0;
 };
 
 namespace {
@@ -129,6 +134,7 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   double *ee = pl.take<double>((size_t)N * B);
   double *elam = pl.take<double>((size_t)N * B);
   double *eS = pl.take<double>(B);
+  int64_t *step_base = pl.take<int64_t>(B);
   float *pr32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   float *pi32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   if (!c) return;
@@ -136,6 +142,7 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy;
   c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
   c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
+  c->step_base = step_base;
   c->eig = EigWork{G, ev, ew, ed, ee, elam, eS};
   c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
   c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
@@ -287,6 +294,32 @@ mfq_status entropy_dev(mfq_ctx *c, const int32_t *region, int32_t n, double *S_h
 }
 
 
+mfq_status validate_step(mfq_ctx *c, int protocol, const double *gamma, double dt, int n_steps) {
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (protocol != MFQ_PROJECTIVE && protocol != MFQ_HOMODYNE) return fail(c, MFQ_EINVAL, "bad protocol");
+  if (!gamma) return fail(c, MFQ_EINVAL, "gamma is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, MFQ_EINVAL, "dt must be positive and finite");
+  if (n_steps < 0) return fail(c, MFQ_EINVAL, "n_steps < 0");
+  for (int b = 0; b < c->B; ++b)
+    if (!(gamma[b] >= 0.0) || !std::isfinite(gamma[b])) return fail(c, MFQ_EINVAL, "gamma must be >= 0");
+  return MFQ_OK;
+}
+
+// Propagator for dt and the monitoring rates on the device.
+mfq_status prepare_step(mfq_ctx *c, const double *gamma, double dt) {
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (!(dt == c->dt_cached)) {
+    mfq_status st = build_propagator(c, dt);
+    if (st) return st;
+  }
+  if (std::memcmp(c->gamma_host.data(), gamma, c->B * sizeof(double)) != 0) {
+    std::memcpy(c->gamma_host.data(), gamma, c->B * sizeof(double));
+    HIPCHK(hipMemcpyAsync(c->gamma, c->gamma_host.data(), c->B * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream), "gamma upload");
+  }
+  return MFQ_OK;
+}
+
 // Enqueue one step on the stream (state X[cur] -> X[1-cur]); the step index is
 // read on the device as *step_dev + step_offset.
 mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int step_offset) {
@@ -310,10 +343,11 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
     PhaseTimer t(c, MFQ_PHASE_MEASURE);
     if (protocol == MFQ_HOMODYNE) {
       HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
-                           c->stream), "homodyne");
+                           c->step_base, c->stream), "homodyne");
     } else {
-      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset, c->pm_sites,
-                        c->pm_out, c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream), "projective");
+      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset, c->step_base,
+                        c->pm_sites, c->pm_out, c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream),
+             "projective");
     }
   }
   {
@@ -397,6 +431,7 @@ mfq_status mfq_destroy(mfq_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   drop_graph(c);
+  if (c->run_S) (void)hipFree(c->run_S);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -486,6 +521,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
          "occupied upload");
   HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
   HIPCHK(fill_zero(c->pm_cnt, ((size_t)n_traj * sizeof(int) + 7) / 8 * 8, c->stream), "event clear");
+  HIPCHK(fill_zero(c->step_base, (size_t)n_traj * sizeof(int64_t), c->stream), "step base clear");
   HIPCHK(init_state(c->X[0], L, N, n_traj, c->occ, c->stream), "init_state");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   c->ready = true;
@@ -495,24 +531,11 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
 mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                     int32_t n_steps) {
   if (!c) return MFQ_EINVAL;
-  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
-  if (protocol != MFQ_PROJECTIVE && protocol != MFQ_HOMODYNE) return fail(c, MFQ_EINVAL, "bad protocol");
-  if (!gamma) return fail(c, MFQ_EINVAL, "gamma is NULL");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, MFQ_EINVAL, "dt must be positive and finite");
-  if (n_steps < 0) return fail(c, MFQ_EINVAL, "n_steps < 0");
-  for (int b = 0; b < c->B; ++b)
-    if (!(gamma[b] >= 0.0) || !std::isfinite(gamma[b])) return fail(c, MFQ_EINVAL, "gamma must be >= 0");
+  mfq_status sv = validate_step(c, protocol, gamma, dt, n_steps);
+  if (sv) return sv;
   if (n_steps == 0) return MFQ_OK;
-  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
-  if (!(dt == c->dt_cached)) {
-    mfq_status st = build_propagator(c, dt);
-    if (st) return st;
-  }
-  if (std::memcmp(c->gamma_host.data(), gamma, c->B * sizeof(double)) != 0) {
-    std::memcpy(c->gamma_host.data(), gamma, c->B * sizeof(double));
-    HIPCHK(hipMemcpyAsync(c->gamma, c->gamma_host.data(), c->B * sizeof(double), hipMemcpyHostToDevice,
-                          c->stream), "gamma upload");
-  }
+  mfq_status st0 = prepare_step(c, gamma, dt);
+  if (st0) return st0;
   HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
   int done = 0;
   if (c->use_graphs && !c->profiling && n_steps >= 2) {
@@ -526,6 +549,92 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
   }
   c->step += n_steps;
+  return MFQ_OK;
+}
+
+mfq_status mfq_set_path(mfq_ctx *c, int32_t path) {
+  if (!c) return MFQ_EINVAL;
+  if (path != MFQ_PATH_AUTO && path != MFQ_PATH_FUSED && path != MFQ_PATH_LAUNCHES)
+    return fail(c, MFQ_EINVAL, "unknown path");
+  c->run_path = path;
+  return MFQ_OK;
+}
+
+mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                   int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
+                   double *S_host, int32_t *n_obs_out) {
+  if (!c) return MFQ_EINVAL;
+  mfq_status st = validate_step(c, protocol, gamma, dt, n_steps);
+  if (st) return st;
+  if (obs_every < 0) return fail(c, MFQ_EINVAL, "obs_every < 0");
+  if (obs_every > 0) {
+    if ((st = validate_region(c, region, n_sites))) return st;
+  }
+  int n_obs = 0;
+  if (obs_every > 0)
+    n_obs = (int)((c->step + n_steps) / obs_every - c->step / obs_every);
+  if (n_obs > 0 && !S_host) return fail(c, MFQ_EINVAL, "S_host is NULL");
+  if (n_obs_out) *n_obs_out = n_obs;
+  if (n_steps == 0) return MFQ_OK;
+  const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+  const bool fits = fused_fits(c->L, c->N, c->lat.Lx, Ly);
+  if (c->run_path == MFQ_PATH_FUSED && !fits)
+    return fail(c, MFQ_EINVAL, "problem does not fit the fused path (LDS)");
+  const bool fused = c->run_path == MFQ_PATH_FUSED || (c->run_path == MFQ_PATH_AUTO && fits);
+  if (!fused) {
+    int done = 0, k = 0;
+    while (done < n_steps) {
+      int chunk = n_steps - done;
+      if (obs_every > 0) chunk = std::min<int64_t>(chunk, obs_every - c->step % obs_every);
+      if ((st = mfq_step(c, protocol, gamma, dt, seed, chunk))) return st;
+      done += chunk;
+      if (obs_every > 0 && c->step % obs_every == 0) {
+        if ((st = entropy_dev(c, region, n_sites, S_host + (size_t)k * c->B))) return st;
+        ++k;
+      }
+    }
+    return check_flag(c);
+  }
+  if ((st = prepare_step(c, gamma, dt))) return st;
+  const size_t need = (size_t)std::max(n_obs, 1) * c->B;
+  if (need > c->run_S_cap) {
+    if (c->run_S) (void)hipFree(c->run_S);
+    c->run_S = nullptr;
+    c->run_S_cap = 0;
+    HIPCHK(hipMalloc(&c->run_S, need * sizeof(double)), "observation buffer");
+    c->run_S_cap = need;
+  }
+  if (obs_every > 0 && n_sites > 0)
+    HIPCHK(hipMemcpyAsync(c->region, region, n_sites * sizeof(int), hipMemcpyHostToDevice, c->stream),
+           "region upload");
+  FusedArgs a{};
+  a.P = c->P; a.U = c->X[c->cur]; a.L = c->L; a.N = c->N;
+  a.gx = c->gx; a.gy = c->gy; a.Lx = c->lat.Lx; a.Ly = Ly;
+  a.gamma = c->gamma; a.dt = dt; a.seed = seed; a.uid = c->uid; a.step_base = c->step_base;
+  a.step0 = c->step; a.n_steps = n_steps; a.protocol = protocol;
+  a.obs_every = obs_every; a.region = c->region; a.nreg = obs_every > 0 ? n_sites : 0;
+  a.max_obs = n_obs; a.S_out = c->run_S;
+  a.ev_sites = c->pm_sites; a.ev_out = c->pm_out; a.ev_cnt = c->pm_cnt; a.ev_prob = c->pm_prob;
+  a.flag = c->flag;
+  {
+    PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
+    HIPCHK(fused_run(a, c->B, c->stream), "fused trajectory kernel");
+  }
+  if (n_obs > 0)
+    HIPCHK(hipMemcpyAsync(S_host, c->run_S, (size_t)n_obs * c->B * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream), "observation download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  c->step += n_steps;
+  return check_flag(c);
+}
+
+mfq_status mfq_reset_trajectory(mfq_ctx *c, int32_t slot, uint64_t uid) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (slot < 0 || slot >= c->B) return fail(c, MFQ_EINVAL, "slot out of range");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(reset_slot(c->X[c->cur], c->L, c->N, slot, c->occ, c->uid, uid, c->step_base, c->step, c->stream),
+         "reset slot");
   return MFQ_OK;
 }
 

@@ -20,7 +20,8 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
 
 // Projective measurements of one step on one trajectory (Appendix A, Eq. (A1),
 // Eq. (A2) with the sign fixed), by the whole workgroup.  Ub: column-major L x N
-// state; site/outcomes/probs: at least L entries; v: N scratch; w: L scratch.
+// state with leading dimension ld; site/outcomes/probs: at least L entries;
+// v: N scratch; w: L scratch.
 // Sites are selected with probability q (Philox purpose 0, word 0) and
 // projected in ascending order, each with its conditional Born probability
 // p = |row j|^2: x = conj(row j), Householder H = I - tau v v^+ with
@@ -29,7 +30,7 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
 // column 0 renormalised.  Returns the number of measured sites.
 __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed, uint64_t key1,
                                 uint64_t step, int *site, int *outcomes, double *probs, cplx *v,
-                                cplx *w) {
+                                cplx *w, int ld) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ int wave_cnt[4];
   __shared__ int total;
@@ -64,7 +65,7 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
     // x = conj(row j), |x|^2
     double part = 0.0;
     for (int k = tid; k < N; k += 256) {
-      const cplx a = Ub[j + (long)k * L];
+      const cplx a = Ub[j + (long)k * ld];
       v[k] = cplx{a.re, -a.im};
       part += a.re * a.re + a.im * a.im;
     }
@@ -101,7 +102,7 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
     for (int i = tid; i < L; i += 256) {
       double ar = 0.0, ai = 0.0;
       for (int k = 0; k < N; ++k) {
-        const cplx u = Ub[i + (long)k * L], vk = v[k];
+        const cplx u = Ub[i + (long)k * ld], vk = v[k];
         ar += u.re * vk.re - u.im * vk.im;
         ai += u.re * vk.im + u.im * vk.re;
       }
@@ -112,7 +113,7 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
     for (int i = tid; i < L; i += 256) {
       const cplx wi = w[i];
       for (int k = 1; k < N; ++k) {
-        cplx u = Ub[i + (long)k * L];
+        cplx u = Ub[i + (long)k * ld];
         const cplx vk = v[k];
         if (i == j) {
           u = cplx{0.0, 0.0};
@@ -120,7 +121,7 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
           u.re -= wi.re * vk.re + wi.im * vk.im;
           u.im -= wi.im * vk.re - wi.re * vk.im;
         }
-        Ub[i + (long)k * L] = u;
+        Ub[i + (long)k * ld] = u;
       }
       cplx c0;
       if (outcome == 1) {

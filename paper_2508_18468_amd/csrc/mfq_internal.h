@@ -50,13 +50,18 @@ hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t 
 // The absolute step index n of a step is read on the device as *step_ptr + step_offset,
 // so that a captured graph of steps can be replayed unchanged.
 hipError_t set_step(int64_t *step_ptr, int64_t value, bool add, hipStream_t s);
+// step_base[b] (per trajectory) is subtracted: trajectory b's own step index is
+// *step_ptr + step_offset - step_base[b].
 hipError_t born_homodyne(cplx *U, double *p, int L, int N, int B, const double *gamma, double dt,
                          uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
-                         hipStream_t s);
+                         const int64_t *step_base, hipStream_t s);
+hipError_t reset_slot(cplx *U, int L, int N, int slot, const int *occ, uint64_t *uid, uint64_t new_uid,
+                      int64_t *step_base, int64_t base, hipStream_t s);
 hipError_t born_only(const cplx *U, double *p, int L, int N, int B, hipStream_t s);
 hipError_t pm_measure(cplx *U, int L, int N, int B, const double *gamma, double dt, uint64_t seed,
-                      const uint64_t *uid, const int64_t *step_ptr, int step_offset, int *sites,
-                      int *outcomes, double *probs, int *counts, cplx *vbuf, cplx *wbuf, hipStream_t s);
+                      const uint64_t *uid, const int64_t *step_ptr, int step_offset,
+                      const int64_t *step_base, int *sites, int *outcomes, double *probs, int *counts,
+                      cplx *vbuf, cplx *wbuf, hipStream_t s);
 hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- Cholesky-QR
@@ -77,6 +82,32 @@ constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
 // factorisation runs.  The choice is made on the device.
 hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &w,
                        bool near_identity, hipStream_t s);
+
+// ---------------------------------------------------------------- fused small-lattice path
+struct FusedArgs {
+  const cplx *P;
+  const cplx *gx, *gy;      // generating rows of P: P = P_y (x) P_x (1d: gy = {1})
+  int Lx, Ly;
+  cplx *U;                  // L x N per trajectory, updated in place
+  int L, N;
+  const double *gamma;
+  double dt;
+  uint64_t seed;
+  const uint64_t *uid;
+  const int64_t *step_base; // per-trajectory step base (trajectory step = context step - base)
+  int64_t step0;            // absolute index of the last completed step
+  int n_steps, protocol;
+  int obs_every;            // observe S after steps n with n % obs_every == 0 (0: never)
+  const int *region;
+  int nreg, max_obs;
+  double *S_out;            // [obs][trajectory]
+  int *ev_sites, *ev_out, *ev_cnt;  // projective events of the last step (L per trajectory)
+  double *ev_prob;
+  int *flag;
+};
+bool fused_fits(int L, int N, int Lx, int Ly);
+size_t fused_lds_bytes(int L, int N, int Lx, int Ly);
+hipError_t fused_run(const FusedArgs &a, int B, hipStream_t s);
 
 // ---------------------------------------------------------------- eigen / entropy
 struct EigWork {

@@ -51,7 +51,7 @@ template <bool HOMODYNE>
 __global__ __launch_bounds__(256) void born_kernel(cplx *U, double *p, int L, int N,
                                                    const double *gamma, double dt, uint64_t seed,
                                                    const uint64_t *uid, const int64_t *step_ptr,
-                                                   int step_offset) {
+                                                   int step_offset, const int64_t *step_base) {
   const int b = blockIdx.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= L) return;
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void born_kernel(cplx *U, double *p, int L, in
   p[(long)b * L + i] = pi;
   if (!HOMODYNE) return;
   const double g = gamma[b];
-  const uint64_t step = (uint64_t)(*step_ptr + step_offset);
+  const uint64_t step = (uint64_t)(*step_ptr + step_offset - step_base[b]);
   const u64x4 w = philox4x64_10(seed, uid[b], step, (uint64_t)i, PURPOSE_HOMODYNE, 0);
   const double z = sqrt(-2.0 * log(u01(w.v[0]))) * cos(6.283185307179586 * u01(w.v[1]));
   const double f = exp(sqrt(g * dt) * z + g * (2.0 * pi - 1.0) * dt);
@@ -91,15 +91,31 @@ __global__ __launch_bounds__(256) void born_kernel(cplx *U, double *p, int L, in
 __global__ __launch_bounds__(256) void pm_kernel(cplx *U, int L, int N, const double *gamma,
                                                  double dt, uint64_t seed, const uint64_t *uid,
                                                  const int64_t *step_ptr, int step_offset,
-                                                 int *sites, int *outcomes,
+                                                 const int64_t *step_base, int *sites, int *outcomes,
                                                  double *probs, int *counts, cplx *vbuf,
                                                  cplx *wbuf) {
   const int b = blockIdx.x;
-  const uint64_t step = (uint64_t)(*step_ptr + step_offset);
+  const uint64_t step = (uint64_t)(*step_ptr + step_offset - step_base[b]);
   const int cnt = pm_measure_block(U + (long)b * L * N, L, N, fmin(gamma[b] * dt, 1.0), seed, uid[b],
                                    step, sites + (long)b * L, outcomes + (long)b * L,
-                                   probs + (long)b * L, vbuf + (long)b * N, wbuf + (long)b * L);
+                                   probs + (long)b * L, vbuf + (long)b * N, wbuf + (long)b * L, L);
   if (threadIdx.x == 0) counts[b] = cnt;
+}
+
+// Trajectory `slot` back to its initial state U[:, k] = e_{occ[k]}, with a new
+// uid and its own step count restarting at 0 (base = the context's step).
+__global__ void reset_slot_kernel(cplx *U, int L, int N, int slot, const int *occ, uint64_t *uid,
+                                  uint64_t new_uid, int64_t *step_base, int64_t base) {
+  cplx *Us = U + (long)slot * L * N;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long)L * N;
+       idx += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % L), k = (int)(idx / L);
+    Us[idx] = cplx{occ[k] == i ? 1.0 : 0.0, 0.0};
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    uid[slot] = new_uid;
+    step_base[slot] = base;
+  }
 }
 
 __global__ void set_step_kernel(int64_t *step_ptr, int64_t value, int add) {
@@ -107,6 +123,14 @@ __global__ void set_step_kernel(int64_t *step_ptr, int64_t value, int add) {
 }
 
 }  // namespace
+
+hipError_t reset_slot(cplx *U, int L, int N, int slot, const int *occ, uint64_t *uid, uint64_t new_uid,
+                      int64_t *step_base, int64_t base, hipStream_t s) {
+  const int blocks = (int)std::min<long>(((long)L * N + 255) / 256, 1024);
+  hipLaunchKernelGGL(reset_slot_kernel, dim3(blocks), dim3(256), 0, s, U, L, N, slot, occ, uid, new_uid,
+                     step_base, base);
+  return hipGetLastError();
+}
 
 hipError_t set_step(int64_t *step_ptr, int64_t value, bool add, hipStream_t s) {
   hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, s, step_ptr, value, add ? 1 : 0);
@@ -140,25 +164,26 @@ hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t 
 
 hipError_t born_homodyne(cplx *U, double *p, int L, int N, int B, const double *gamma, double dt,
                          uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
-                         hipStream_t s) {
+                         const int64_t *step_base, hipStream_t s) {
   dim3 grid((L + 255) / 256, B);
   hipLaunchKernelGGL(born_kernel<true>, grid, dim3(256), 0, s, U, p, L, N, gamma, dt, seed, uid,
-                     step_ptr, step_offset);
+                     step_ptr, step_offset, step_base);
   return hipGetLastError();
 }
 
 hipError_t born_only(const cplx *U, double *p, int L, int N, int B, hipStream_t s) {
   dim3 grid((L + 255) / 256, B);
   hipLaunchKernelGGL(born_kernel<false>, grid, dim3(256), 0, s, const_cast<cplx *>(U), p, L, N,
-                     nullptr, 0.0, 0ull, nullptr, nullptr, 0);
+                     nullptr, 0.0, 0ull, nullptr, nullptr, 0, nullptr);
   return hipGetLastError();
 }
 
 hipError_t pm_measure(cplx *U, int L, int N, int B, const double *gamma, double dt, uint64_t seed,
-                      const uint64_t *uid, const int64_t *step_ptr, int step_offset, int *sites,
-                      int *outcomes, double *probs, int *counts, cplx *vbuf, cplx *wbuf, hipStream_t s) {
+                      const uint64_t *uid, const int64_t *step_ptr, int step_offset,
+                      const int64_t *step_base, int *sites, int *outcomes, double *probs, int *counts,
+                      cplx *vbuf, cplx *wbuf, hipStream_t s) {
   hipLaunchKernelGGL(pm_kernel, dim3(B), dim3(256), 0, s, U, L, N, gamma, dt, seed, uid, step_ptr,
-                     step_offset, sites, outcomes, probs, counts, vbuf, wbuf);
+                     step_offset, step_base, sites, outcomes, probs, counts, vbuf, wbuf);
   return hipGetLastError();
 }
 

@@ -34,6 +34,20 @@ class Lattice(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("J", ctypes.c_double)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("lat", Lattice), ("N", ctypes.c_int32), ("protocol", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("n_steps", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("n_region", ctypes.c_int32), ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("uid", ctypes.c_uint64), ("region", ctypes.c_void_p)]
+
+
+class EngineStats(ctypes.Structure):
+    _fields_ = [("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("queued", ctypes.c_int64), ("groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+MFQ_PENDING = 1
 _lib = None
 
 _SIGS = {
@@ -60,6 +74,20 @@ _SIGS = {
     "mfq_synchronize": (ctypes.c_int32, [ctypes.c_void_p]),
     "mfq_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_use_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                 ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_set_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_reset_trajectory": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
+    "mfq_engine_create": (ctypes.c_int32, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p)]),
+    "mfq_engine_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "mfq_engine_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "mfq_engine_submit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]),
+    "mfq_engine_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "mfq_engine_wait": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double]),
+    "mfq_engine_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(EngineStats)]),
     "mfq_phase_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
@@ -69,11 +97,17 @@ EXPORTED = tuple(_SIGS)
 
 
 def lib():
-    """Load libmfq.so (built in-tree by __graft_entry__.build()); raise if absent."""
+    """Load libmfq.so (built in-tree by __graft_entry__.build()); raise if absent.
+
+    PyTorch is imported first: its bundled HIP runtime carries the same soname as
+    the one libmfq links against, so loading torch first makes both use one
+    runtime (loading libmfq first would put two HIP runtimes in the process).
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        import torch  # noqa: F401  (one HIP runtime per process, see above)
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(l, name)
@@ -182,6 +216,32 @@ def mfq_synchronize(ctx):
     _check(ctx, lib().mfq_synchronize(ctx))
 
 
+PATH_AUTO, PATH_FUSED, PATH_LAUNCHES = 0, 1, 2
+
+
+def mfq_run(ctx, protocol, gamma, dt, seed, n_steps, obs_every, region, n_traj, step_now):
+    """Returns S as an (n_obs, n_traj) array."""
+    g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    r = _i32(region if region is not None else [])
+    n_obs_expected = 0
+    if obs_every > 0:
+        n_obs_expected = (step_now + n_steps) // obs_every - step_now // obs_every
+    S = np.zeros((max(n_obs_expected, 1), n_traj))
+    n_obs = ctypes.c_int32()
+    _check(ctx, lib().mfq_run(ctx, protocol, _ptr(g), float(dt), int(seed), int(n_steps), int(obs_every),
+                              _ptr(r), r.size, _ptr(S), ctypes.byref(n_obs)))
+    assert n_obs.value == n_obs_expected
+    return S[:n_obs.value]
+
+
+def mfq_reset_trajectory(ctx, slot, uid):
+    _check(ctx, lib().mfq_reset_trajectory(ctx, int(slot), int(uid)))
+
+
+def mfq_set_path(ctx, path):
+    _check(ctx, lib().mfq_set_path(ctx, int(path)))
+
+
 def mfq_use_graphs(ctx, enable):
     _check(ctx, lib().mfq_use_graphs(ctx, 1 if enable else 0))
 
@@ -195,6 +255,65 @@ def mfq_phase_times(ctx):
     cnt = np.zeros(len(PHASES), dtype=np.int64)
     _check(ctx, lib().mfq_phase_times(ctx, _ptr(ms), _ptr(cnt)))
     return {ph: (float(ms[i]), int(cnt[i])) for i, ph in enumerate(PHASES)}
+
+
+# ------------------------------------------------------------------ serving engine
+
+class Engine:
+    """Continuous-batching engine of the library (worker thread inside libmfq)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, max_slots=16):
+        out = ctypes.c_void_p()
+        _check(None, lib().mfq_engine_create(device, hbm_budget_bytes, max_slots, ctypes.byref(out)))
+        self.h = out.value
+        self._keep = {}
+
+    def _err(self, code):
+        if code not in (MFQ_OK, MFQ_PENDING):
+            raise MfqError(code, lib().mfq_engine_last_error(self.h).decode())
+
+    def submit(self, dim, Lx, Ly, protocol, gamma, dt, n_steps, seed, uid, region, obs_every=0,
+               precision=FP64, J=1.0):
+        r = _i32(region)
+        j = Job(Lattice(dim, Lx, Ly if dim == 2 else 1, 0, J), 0, protocol, precision, n_steps, obs_every,
+                r.size, float(gamma), float(dt), int(seed), int(uid), r.ctypes.data_as(ctypes.c_void_p))
+        jid = ctypes.c_uint64()
+        self._err(lib().mfq_engine_submit(self.h, ctypes.byref(j), ctypes.byref(jid)))
+        return jid.value
+
+    def poll(self, job_id, max_obs=4096):
+        """None while pending, else (S array, latency seconds)."""
+        S = np.zeros(max_obs)
+        n = ctypes.c_int32()
+        lat = ctypes.c_double()
+        code = lib().mfq_engine_poll(self.h, job_id, _ptr(S), max_obs, ctypes.byref(n), ctypes.byref(lat))
+        if code == MFQ_PENDING:
+            return None
+        self._err(code)
+        return S[:n.value].copy(), lat.value
+
+    def wait(self, job_id, timeout_s=600.0):
+        code = lib().mfq_engine_wait(self.h, job_id, float(timeout_s))
+        if code == MFQ_PENDING:
+            raise TimeoutError(f"job {job_id} not done after {timeout_s} s")
+        self._err(code)
+        return self.poll(job_id)
+
+    def stats(self):
+        st = EngineStats()
+        self._err(lib().mfq_engine_stats(self.h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in EngineStats._fields_ if f != "reserved"}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mfq_engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ convenience object
@@ -252,6 +371,23 @@ class Trajectories:
 
     def synchronize(self):
         mfq_synchronize(self.ctx)
+
+    def run(self, protocol, gamma, dt, seed, n_steps, obs_every=0, region=None):
+        g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (self.n_traj,))
+        return mfq_run(self.ctx, protocol, g, dt, seed, n_steps, obs_every, region, self.n_traj,
+                       self.step_index())
+
+    def step_index(self):
+        step = ctypes.c_int64()
+        _check(self.ctx, lib().mfq_get_state(self.ctx, None, ctypes.byref(step)))
+        return step.value
+
+    def reset_trajectory(self, slot, uid):
+        mfq_reset_trajectory(self.ctx, slot, uid)
+        self.uids[slot] = uid
+
+    def set_path(self, path):
+        mfq_set_path(self.ctx, path)
 
     def use_graphs(self, enable=True):
         mfq_use_graphs(self.ctx, enable)
