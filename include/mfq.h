@@ -114,8 +114,10 @@ mfq_status mfq_init_state(mfq_ctx *ctx, const mfq_lattice *lat, int32_t N, int32
  * waiting times instead).  Homodyne: rows of U are scaled by
  * exp(xi_i + gamma (2<n_i> - 1) dt), xi_i ~ N(0, gamma dt) (Eq. (A4), applied
  * after the propagator).  The propagator exp(-i Ht dt) is rebuilt when dt
- * changes.  Asynchronous; numeric failures (Cholesky breakdown) surface as
- * MFQ_ENUMERIC from the next synchronising call.
+ * changes.  Asynchronous, except projective steps in the blocked form (see
+ * mfq_set_pm_path), which synchronise the stream twice per step; numeric
+ * failures (Cholesky breakdown) surface as MFQ_ENUMERIC from the next
+ * synchronising call.
  * Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_EDEVICE. */
 mfq_status mfq_step(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                     int32_t n_steps);
@@ -174,6 +176,26 @@ mfq_status mfq_synchronize(mfq_ctx *ctx);
 mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out);
+
+/* How projective measurements of a step are carried out (Appendix A, Eq. (A1),
+ * Eq. (A2) sign-corrected).  Both forms give the same outcomes and
+ * conditional probabilities from the same random numbers, and the same state
+ * up to the choice of orthonormal basis of its orbital space.
+ *   MFQ_PM_WORKGROUP  one workgroup per trajectory projects the measured
+ *                     sites one after another (each a pass over U);
+ *   MFQ_PM_BLOCKED    the outcomes are drawn from C_MM = U_M U_M^+ of the
+ *                     measured sites M by sequential elimination, then U is
+ *                     updated at once: LQ of the outcome-1 rows and a
+ *                     compact-WY product on the matrix cores.  The host reads
+ *                     the per-step counts (two stream synchronisations per
+ *                     step; such steps are not graph-replayed).  Needs N >= 128
+ *                     and at most N measured sites in a step, else the step
+ *                     falls back to the workgroup form;
+ *   MFQ_PM_AUTO       blocked for L >= 2048, workgroup below (default). */
+#define MFQ_PM_AUTO 0
+#define MFQ_PM_WORKGROUP 1
+#define MFQ_PM_BLOCKED 2
+mfq_status mfq_set_pm_path(mfq_ctx *ctx, int32_t path);
 
 #define MFQ_PATH_AUTO 0     /* fused when the problem fits in LDS, else per-phase kernels */
 #define MFQ_PATH_FUSED 1    /* force the fused single-launch path (MFQ_EINVAL if it does not fit) */

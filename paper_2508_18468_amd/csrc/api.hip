@@ -41,6 +41,8 @@ struct mfq_ctx {
   int *pm_sites = nullptr, *pm_out = nullptr, *pm_cnt = nullptr;
   double *pm_prob = nullptr;
   cplx *pm_v = nullptr, *pm_w = nullptr;
+  PmBlockedWork pmb{};
+  int pm_path = 0;  // MFQ_PM_AUTO
   std::vector<double> gamma_host;
   // phase timing
   bool profiling = false;
@@ -128,8 +130,15 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   double *pm_prob = pl.take<double>((size_t)L * B);
   cplx *pm_v = pl.take<cplx>((size_t)N * B);
   cplx *pm_w = pl.take<cplx>((size_t)L * B);
-  cplx *ev = pl.take<cplx>((size_t)N * B);
+  double *pm_u = pl.take<double>((size_t)L * B);
+  double *pm_tau = pl.take<double>((size_t)L * B);
+  int *pm_m1 = pl.take<int>((size_t)L * B);
+  int *pm_k1 = pl.take<int>(B);
+  int *pm_code = pl.take<int>((size_t)L * B);
+  cplx *ev = pl.take<cplx>((size_t)2 * N * B);
   cplx *ew = pl.take<cplx>((size_t)N * B);
+  cplx *ep = pl.take<cplx>((size_t)N * B);
+  double *etau = pl.take<double>((size_t)2 * B);
   double *ed = pl.take<double>((size_t)N * B);
   double *ee = pl.take<double>((size_t)N * B);
   double *elam = pl.take<double>((size_t)N * B);
@@ -143,10 +152,12 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
   c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
   c->step_base = step_base;
-  c->eig = EigWork{G, ev, ew, ed, ee, elam, eS};
+  c->eig = EigWork{G, ev, ew, ep, etau, ed, ee, elam, eS};
   c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
   c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
   c->pm_v = pm_v; c->pm_w = pm_w;
+  c->pmb = PmBlockedWork{pm_sites, pm_out, pm_cnt, pm_prob, pm_u, pm_tau, pm_m1, pm_k1, pm_code,
+                         G, Rinv, T};
 }
 
 // Generating row of the ring propagator exp(-i Ht dt) from the Jacobi-Anger
@@ -320,6 +331,14 @@ mfq_status prepare_step(mfq_ctx *c, const double *gamma, double dt) {
   return MFQ_OK;
 }
 
+// Projective steps of large lattices use the blocked measurement (it
+// synchronises the stream, so such steps are never captured in a graph).
+constexpr int PM_BLOCKED_MIN_L = 2048;
+bool blocked_pm(const mfq_ctx *c) {
+  if (c->pm_path == MFQ_PM_BLOCKED) return true;
+  return c->pm_path == MFQ_PM_AUTO && c->L >= PM_BLOCKED_MIN_L;
+}
+
 // Enqueue one step on the stream (state X[cur] -> X[1-cur]); the step index is
 // read on the device as *step_dev + step_offset.
 mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int step_offset) {
@@ -345,9 +364,14 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
       HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
                            c->step_base, c->stream), "homodyne");
     } else {
-      HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset, c->step_base,
-                        c->pm_sites, c->pm_out, c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w, c->stream),
-             "projective");
+      bool fallback = true;
+      if (blocked_pm(c))
+        HIPCHK(pm_blocked(Xb, Xa, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
+                          c->step_base, c->pmb, &fallback, c->stream), "projective (blocked)");
+      if (fallback)
+        HIPCHK(pm_measure(Xb, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
+                          c->step_base, c->pm_sites, c->pm_out, c->pm_prob, c->pm_cnt, c->pm_v, c->pm_w,
+                          c->stream), "projective");
     }
   }
   {
@@ -538,7 +562,8 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
   if (st0) return st0;
   HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
   int done = 0;
-  if (c->use_graphs && !c->profiling && n_steps >= 2) {
+  const bool capturable = !(protocol == MFQ_PROJECTIVE && blocked_pm(c));
+  if (c->use_graphs && !c->profiling && n_steps >= 2 && capturable) {
     mfq_status st = ensure_step_graph(c, protocol, dt, seed);
     if (st) return st;
     for (; done + 2 <= n_steps; done += 2) HIPCHK(hipGraphLaunch(c->gexec, c->stream), "graph launch");
@@ -549,6 +574,14 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
   }
   c->step += n_steps;
+  return MFQ_OK;
+}
+
+mfq_status mfq_set_pm_path(mfq_ctx *c, int32_t path) {
+  if (!c) return MFQ_EINVAL;
+  if (path != MFQ_PM_AUTO && path != MFQ_PM_WORKGROUP && path != MFQ_PM_BLOCKED)
+    return fail(c, MFQ_EINVAL, "unknown projective-measurement path");
+  c->pm_path = path;
   return MFQ_OK;
 }
 

@@ -18,6 +18,44 @@ __device__ __forceinline__ double block_sum256(double v, double *red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Maximum over the 256 threads of a workgroup; every thread receives it.
+__device__ __forceinline__ double block_max256(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// Vectors whose largest component is below this are treated as zero when a
+// reflector is formed (dropping them changes the result by less than that).
+constexpr double REFLECT_TINY = 1e-290;
+
+// Householder reflector H = I - tau v v^+ with H x = alpha e_0,
+// alpha = -phase(x_0)|x|, v = x - alpha e_0, formed from the vector scaled by
+// s = its largest component magnitude (s >= REFLECT_TINY): x0s = x_0 / s,
+// tail2s = sum_{i>=1} |x_i / s|^2.  The returned v0 is the first entry of the
+// scaled v (the other entries are x_i / s) and tau belongs to the scaled v;
+// norm = |x|.  Scaling keeps every square away from underflow, so tau is
+// consistent with v and H is unitary to rounding for any magnitude of x.
+struct Reflector {
+  cplx v0;
+  double tau, norm;
+};
+__device__ __forceinline__ Reflector make_reflector(cplx x0s, double tail2s, double s) {
+  const double ax0 = hypot(x0s.re, x0s.im);
+  const double nx = sqrt(ax0 * ax0 + tail2s);
+  const double phr = ax0 > 0.0 ? x0s.re / ax0 : 1.0, phi = ax0 > 0.0 ? x0s.im / ax0 : 0.0;
+  Reflector r;
+  r.v0 = cplx{x0s.re + phr * nx, x0s.im + phi * nx};
+  r.tau = 2.0 / (tail2s + r.v0.re * r.v0.re + r.v0.im * r.v0.im);
+  r.norm = s * nx;
+  return r;
+}
+
+__device__ __forceinline__ double cmax_abs(cplx a) { return fmax(fabs(a.re), fabs(a.im)); }
+
 // Projective measurements of one step on one trajectory (Appendix A, Eq. (A1),
 // Eq. (A2) with the sign fixed), by the whole workgroup.  Ub: column-major L x N
 // state with leading dimension ld; site/outcomes/probs: at least L entries;
@@ -62,37 +100,44 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
 
   for (int e = 0; e < cnt; ++e) {
     const int j = site[e];
-    // x = conj(row j), |x|^2
-    double part = 0.0;
+    // x = conj(row j), p = |x|^2, s = largest component
+    double part = 0.0, mx = 0.0;
     for (int k = tid; k < N; k += 256) {
       const cplx a = Ub[j + (long)k * ld];
       v[k] = cplx{a.re, -a.im};
       part += a.re * a.re + a.im * a.im;
+      mx = fmax(mx, cmax_abs(a));
     }
     const double p = block_sum256(part, red);
+    const double s = block_max256(mx, red);
+    // the reflector is formed from x / s (each thread rescales its own entries)
+    double part2 = 0.0;
+    if (s >= REFLECT_TINY) {
+      const double inv = 1.0 / s;
+      for (int k = tid; k < N; k += 256) {
+        const cplx a{v[k].re * inv, v[k].im * inv};
+        v[k] = a;
+        if (k >= 1) part2 += a.re * a.re + a.im * a.im;
+      }
+    }
+    const double tail2 = block_sum256(part2, red);
     if (tid == 0) {
       const u64x4 r = philox4x64_10(seed, key1, step, (uint64_t)j, PURPOSE_PROJECTIVE, 0);
       const int outcome = (u01(r.v[1]) <= p) ? 1 : 0;
       sh_outcome = outcome;
       outcomes[e] = outcome;
       probs[e] = p;
-      const cplx x0 = v[0];
-      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im);
-      const double nx = sqrt(p);
-      if (nx == 0.0) {
+      if (!(s >= REFLECT_TINY)) {
         sh_skip = 1;
       } else {
         sh_skip = 0;
-        const double phr = ax0 > 0.0 ? x0.re / ax0 : 1.0, phi = ax0 > 0.0 ? x0.im / ax0 : 0.0;
-        const double br = -phr * nx, bi = -phi * nx;  // beta
-        const double v0r = x0.re - br, v0i = x0.im - bi;
-        const double vn2 = (p - ax0 * ax0) + (v0r * v0r + v0i * v0i);
-        sh_tau = 2.0 / vn2;
-        v[0] = cplx{v0r, v0i};
+        const Reflector h = make_reflector(v[0], tail2, s);
+        sh_tau = h.tau;
+        v[0] = h.v0;
       }
     }
     __syncthreads();
-    if (sh_skip) {  // empty row: p = 0, outcome 0 leaves the state unchanged
+    if (sh_skip) {  // empty row (below REFLECT_TINY): outcome 0 leaves the state unchanged
       __syncthreads();
       continue;
     }
@@ -167,27 +212,31 @@ __device__ inline void tridiag_body(cplx *A, int ld, int n, cplx *v, cplx *p, do
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     cplx *x = A + (k + 1) + (long)k * ld;
+    double mx = 0.0;
+    for (int i = tid; i < m; i += 256) mx = fmax(mx, cmax_abs(x[i]));
+    const double s = block_max256(mx, red);
+    const double inv = s >= REFLECT_TINY ? 1.0 / s : 0.0;
     double part = 0.0;
-    for (int i = 1 + tid; i < m; i += 256) part += x[i].re * x[i].re + x[i].im * x[i].im;
+    for (int i = 1 + tid; i < m; i += 256) {
+      const cplx a{x[i].re * inv, x[i].im * inv};
+      v[i] = a;
+      part += a.re * a.re + a.im * a.im;
+    }
     const double tail2 = block_sum256(part, red);
     if (tid == 0) {
       const cplx x0 = x[0];
-      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im);
       d[k] = A[k + (long)k * ld].re;
-      if (tail2 == 0.0) {
-        e[k] = ax0;
+      if (tail2 == 0.0) {  // nothing below x0 (or all below REFLECT_TINY): H = I
+        e[k] = hypot(x0.re, x0.im);
         s_skip = 1;
       } else {
-        const double nx = sqrt(ax0 * ax0 + tail2);
-        const double phr = ax0 > 0.0 ? x0.re / ax0 : 1.0, phi = ax0 > 0.0 ? x0.im / ax0 : 0.0;
-        const double v0r = x0.re + phr * nx, v0i = x0.im + phi * nx;
-        s_tau = 2.0 / (tail2 + v0r * v0r + v0i * v0i);
-        e[k] = nx;
+        const Reflector h = make_reflector(cplx{x0.re * inv, x0.im * inv}, tail2, s);
+        s_tau = h.tau;
+        e[k] = h.norm;
         s_skip = 0;
-        v[0] = cplx{v0r, v0i};
+        v[0] = h.v0;
       }
     }
-    for (int i = 1 + tid; i < m; i += 256) v[i] = x[i];
     __syncthreads();
     if (s_skip) continue;
     const double tau = s_tau;
@@ -238,7 +287,7 @@ __device__ inline void tridiag_body(cplx *A, int ld, int n, cplx *v, cplx *p, do
     if (n >= 2) {
       d[n - 2] = A[(n - 2) + (long)(n - 2) * ld].re;
       const cplx t = A[(n - 1) + (long)(n - 2) * ld];
-      e[n - 2] = sqrt(t.re * t.re + t.im * t.im);
+      e[n - 2] = hypot(t.re, t.im);
     }
     d[n - 1] = A[(n - 1) + (long)(n - 1) * ld].re;
   }
@@ -258,6 +307,16 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e, int
     if (q < 0.0) ++c;
   }
   return c;
+}
+
+// Estimate from a final bisection bracket [lo, hi].  The spectrum of a region
+// correlation matrix lies in [0, 1]; when the bracket holds 0 or 1 that bound
+// is returned (exact for the 0/1 eigenvalues of product states), otherwise
+// the midpoint.  Either is within the bracket width of the eigenvalue.
+__device__ __forceinline__ double bracket_estimate(double lo, double hi) {
+  if (lo <= 0.0 && 0.0 <= hi) return 0.0;
+  if (lo <= 1.0 && 1.0 <= hi) return 1.0;
+  return 0.5 * (lo + hi);
 }
 
 // Eigenvalue k (ascending) of the tridiagonal (d, e) of order n by bisection on
@@ -281,7 +340,7 @@ __device__ inline double bisect_eigenvalue(const double *d, const double *e, int
     if (sturm_count(d, e, n, mid, pivmin) > k) hi = mid;
     else lo = mid;
   }
-  return 0.5 * (lo + hi);
+  return bracket_estimate(lo, hi);
 }
 
 // h(x) = -x ln x - (1 - x) ln(1 - x) for x clamped to [0, 1] (Sec. II entropy formula).

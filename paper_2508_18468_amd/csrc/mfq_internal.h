@@ -30,6 +30,7 @@ struct GemmDesc {
   int bUpper;              // op(B) is upper triangular: B[k][n] = 0 for k > n
   const double *skip_if_le;  // if set and *skip_if_le <= skip_thr, the launch does nothing
   double skip_thr;
+  long sIdxA, sIdxB;       // batch stride of idxA / idxB (0: one index list for all entries)
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
@@ -63,6 +64,25 @@ hipError_t pm_measure(cplx *U, int L, int N, int B, const double *gamma, double 
                       const int64_t *step_base, int *sites, int *outcomes, double *probs, int *counts,
                       cplx *vbuf, cplx *wbuf, hipStream_t s);
 hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// Blocked projective measurement for large lattices (selection, conditional
+// outcomes from C_MM, LQ of the outcome-1 rows, compact-WY update of U).
+struct PmBlockedWork {
+  int *sites, *outcomes, *counts;  // L, L, 1 per trajectory (the events of the step)
+  double *probs, *udraw, *tau;     // L per trajectory
+  int *m1, *k1, *code;             // L, 1, L per trajectory
+  cplx *G, *R;                     // N x N per trajectory (free during the measurement)
+  cplx *T;                         // N x 64 per trajectory
+};
+// U: L x N per trajectory (updated in place); scratch: L x N per trajectory.
+// Synchronises the stream twice (the host sizes the launches by the counts).
+// *fallback is set, with U untouched, when the step cannot be done in this
+// form (more measured sites than N, or N < 128); the caller then measures
+// with pm_measure.
+hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double *gamma, double dt,
+                      uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
+                      const int64_t *step_base, const PmBlockedWork &w, bool *fallback,
+                      hipStream_t s);
 
 // ---------------------------------------------------------------- Cholesky-QR
 struct CholWork {
@@ -112,7 +132,10 @@ hipError_t fused_run(const FusedArgs &a, int B, hipStream_t s);
 // ---------------------------------------------------------------- eigen / entropy
 struct EigWork {
   cplx *A;      // n x n per trajectory (Gram of the region)
-  cplx *v, *w;  // n per trajectory (Householder scratch)
+  cplx *v;      // 2 n per trajectory: two Householder vector slots
+  cplx *w;      // n per trajectory: w of the pending rank-2 update
+  cplx *p;      // n per trajectory: A v of the newest reflector
+  double *tau;  // 2 per trajectory: tau of the two reflector slots
   double *d, *e, *lam, *S;
 };
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,

@@ -112,6 +112,8 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   const int wr = wave % WM, wc = wave / WM;
   const cplx *A = g.A + (long)b * g.sA;
   const cplx *B = g.B + (long)b * g.sB;
+  const int *idxA = GATHER && g.idxA ? g.idxA + (long)b * g.sIdxA : nullptr;
+  const int *idxB = GATHER && g.idxB ? g.idxB + (long)b * g.sIdxB : nullptr;
 
   // per-thread tile coordinates: element i of this thread is (m_a, k_a + i*da) of the
   // A tile and (k_b + i*db, n_b) of the B tile
@@ -134,10 +136,10 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       if (!EDGE || (gm < g.M && gk < kend)) {
         cplx v;
         if (OPA == OP_N) {
-          const long row = GATHER && g.idxA ? g.idxA[gm] : gm;
+          const long row = idxA ? idxA[gm] : gm;
           v = A[row + (long)gk * g.lda];
         } else {
-          const long row = GATHER && g.idxA ? g.idxA[gk] : gk;
+          const long row = idxA ? idxA[gk] : gk;
           v = A[row + (long)gm * g.lda];
           v.im = -v.im;
         }
@@ -154,10 +156,10 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       if (!EDGE || (gn < g.N && gk < kend)) {
         cplx v;
         if (OPB == OP_N) {
-          const long row = GATHER && g.idxB ? g.idxB[gk] : gk;
+          const long row = idxB ? idxB[gk] : gk;
           v = B[row + (long)gn * g.ldb];
         } else {
-          const long row = GATHER && g.idxB ? g.idxB[gn] : gn;
+          const long row = idxB ? idxB[gn] : gn;
           v = B[row + (long)gk * g.ldb];
           v.im = -v.im;
         }

@@ -78,6 +78,7 @@ _SIGS = {
                                  ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_set_pm_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_reset_trajectory": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
     "mfq_engine_create": (ctypes.c_int32, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_void_p)]),
@@ -238,6 +239,13 @@ def mfq_reset_trajectory(ctx, slot, uid):
     _check(ctx, lib().mfq_reset_trajectory(ctx, int(slot), int(uid)))
 
 
+PM_AUTO, PM_WORKGROUP, PM_BLOCKED = 0, 1, 2
+
+
+def mfq_set_pm_path(ctx, path):
+    _check(ctx, lib().mfq_set_pm_path(ctx, int(path)))
+
+
 def mfq_set_path(ctx, path):
     _check(ctx, lib().mfq_set_path(ctx, int(path)))
 
@@ -388,6 +396,9 @@ class Trajectories:
 
     def set_path(self, path):
         mfq_set_path(self.ctx, path)
+
+    def set_pm_path(self, path):
+        mfq_set_pm_path(self.ctx, path)
 
     def use_graphs(self, enable=True):
         mfq_use_graphs(self.ctx, enable)

@@ -1,0 +1,188 @@
+"""Blocked projective measurement (outcomes drawn from C_MM by sequential elimination, then
+LQ of the outcome-1 rows and a compact-WY update of U) against the oracle's per-site
+Householder projections, against the library's own per-workgroup form, and at the full size
+of the long-chain projective workload (1d ring L=16384) on sampled outputs.
+
+Tolerances as for the other parity tests (identical sites and outcomes, |dS| <= 1e-9,
+invariants within 1e-10), except the conditional probabilities: the blocked form obtains them
+by Gaussian elimination on C_MM with pivots d = p (outcome 1) or p - 1 (outcome 0), which
+amplifies rounding by up to 1/|d| per earlier pivot of the step, while the oracle's per-site
+projections are unitary.  Event t of a step is allowed 1e-12 (1 + sum_{s<t} 1/|d_s|).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.philox import pm_uniforms
+from gpu_common import OracleBatch, make_sim, corr
+from dform import project_outcome0, project_outcome1
+
+pytestmark = pytest.mark.gpu
+
+PM = 0
+
+
+def prob_tols(events):
+    """Allowed |dp| per event of one step (see the module docstring)."""
+    out, acc = [], 1.0
+    for _, p, o in events:
+        out.append(1e-12 * acc)
+        d = p if o == 1 else p - 1.0
+        acc += 1.0 / max(abs(d), 1e-300)
+    return out
+
+
+def _blocked(sim):
+    from paper_2508_18468_amd import mfq
+    sim.set_pm_path(mfq.PM_BLOCKED)
+    return sim
+
+
+@pytest.mark.parametrize("L,gamma,n_steps", [(512, 1.0, 20), (512, 9.0, 6), (600, 0.4, 12)])
+def test_blocked_matches_oracle(L, gamma, n_steps):
+    """L=512 and 600 (N=256, 300): q = gamma dt = 0.05, 0.45 (about 25 and 230 sites a step,
+    the latter close to N), 0.02; three trajectories with different rates."""
+    dt, seed = 0.05, 7
+    uids = [3, 4, 5]
+    gams = [gamma, 0.5 * gamma, 0.25 * gamma]
+    sim = _blocked(make_sim(1, L, n_traj=3, uids=uids))
+    ob = OracleBatch(1, L, 1, dt, uids)
+    regions = [list(range(L // 2)), list(range(0, L, 3))]
+    n_events = 0
+    for n in range(1, n_steps + 1):
+        sim.step(PM, gams, dt, seed)
+        ev_ref = ob.step(PM, gams, seed)
+        ev_gpu = sim.pm_events()
+        for t in range(3):
+            assert [(e[0], e[2]) for e in ev_gpu[t]] == [(e[0], e[2]) for e in ev_ref[t]], (n, t)
+            for a, b, tol in zip(ev_gpu[t], ev_ref[t], prob_tols(ev_ref[t])):
+                assert abs(a[1] - b[1]) <= tol, (n, t, a, b, tol)
+            n_events += len(ev_ref[t])
+        if n % 3 == 0 or n == n_steps:
+            for r in regions:
+                assert np.abs(sim.entropy(r) - ob.entropy(r)).max() <= 1e-9, (n, len(r))
+    assert n_events > 5 * n_steps
+    U, _ = sim.get_state()
+    for t in range(3):
+        assert np.abs(U[t].conj().T @ U[t] - np.eye(L // 2)).max() <= 1e-10
+        assert np.abs(corr(U[t]) - corr(ob.U[t])).max() <= 1e-9
+    sim.close()
+
+
+def test_blocked_equals_workgroup_form():
+    """Same trajectories through both forms: identical events, equal correlation matrices."""
+    from paper_2508_18468_amd import mfq
+    L, dt, seed = 640, 0.05, 11
+    uids = [0, 1]
+    gams = [2.0, 0.7]
+    a = make_sim(1, L, n_traj=2, uids=uids)
+    a.set_pm_path(mfq.PM_WORKGROUP)
+    b = _blocked(make_sim(1, L, n_traj=2, uids=uids))
+    for n in range(10):
+        a.step(PM, gams, dt, seed)
+        b.step(PM, gams, dt, seed)
+        ea, eb = a.pm_events(), b.pm_events()
+        for t in range(2):
+            assert [(e[0], e[2]) for e in ea[t]] == [(e[0], e[2]) for e in eb[t]]
+            for x, y, tol in zip(ea[t], eb[t], prob_tols(ea[t])):
+                assert abs(x[1] - y[1]) <= tol, (n, t, x, y, tol)
+    Ua, _ = a.get_state()
+    Ub, _ = b.get_state()
+    for t in range(2):
+        assert np.abs(corr(Ua[t]) - corr(Ub[t])).max() <= 1e-10
+    r = list(range(200))
+    assert np.abs(a.entropy(r) - b.entropy(r)).max() <= 1e-10
+    a.close()
+    b.close()
+
+
+def test_blocked_step_chunking_is_exact():
+    """n steps in one call equal n calls of one step (the blocked form is not graph-captured)."""
+    L, dt, seed = 512, 0.05, 3
+    a = _blocked(make_sim(1, L, n_traj=2, uids=[8, 9]))
+    b = _blocked(make_sim(1, L, n_traj=2, uids=[8, 9]))
+    a.step(PM, [1.5, 1.0], dt, seed, n_steps=6)
+    for _ in range(6):
+        b.step(PM, [1.5, 1.0], dt, seed)
+    Ua, sa = a.get_state()
+    Ub, sb = b.get_state()
+    assert sa == sb == 6
+    assert np.array_equal(Ua, Ub)
+    a.close()
+    b.close()
+
+
+def _ring_generating_column(L, J, dt):
+    """P[d, 0] of exp(-i Ht dt) on the ring by the plane-wave closed form, via an inverse FFT."""
+    k = 2.0 * np.pi * np.arange(L) / L
+    return np.fft.ifft(np.exp(-2j * J * dt * np.cos(k)))
+
+
+def test_generating_column_matches_oracle_propagator():
+    L, dt = 96, 0.05
+    P = oracle.propagator(oracle.Lattice(1, L, 1), dt)
+    col = _ring_generating_column(L, 1.0, dt)
+    a = np.arange(L)
+    assert np.abs(P - col[(a[:, None] - a[None, :]) % L]).max() < 1e-14
+
+
+def test_long_ring_projective_full_size_sampled():
+    """1d ring L=16384, N=8192, projective, gamma in {0.2, 1.0} (about 164 and 819 measured
+    sites a step), dt = 0.05, seed 0.  Checked on step 2: the selected sites equal the
+    oracle's draws; the first six conditional probabilities equal the sequential Eq. (A1)/(A2)
+    updates of C_MM built on the host from rows of P U (P by the plane-wave closed form);
+    every outcome obeys u <= p; sampled columns of U^+ U equal the identity; the trace of C_A
+    equals the sum of the occupations over A."""
+    import time
+    L, N, dt, seed = 16384, 8192, 0.05, 0
+    gams = [0.2, 1.0]
+    sim = make_sim(1, L, n_traj=2, uids=[0, 1])
+    t0 = time.perf_counter()
+    sim.step(PM, gams, dt, seed)
+    sim.synchronize()
+    t1 = time.perf_counter()
+    U1, step = sim.get_state()
+    assert step == 1
+    sim.step(PM, gams, dt, seed)
+    sim.synchronize()
+    t2 = time.perf_counter()
+    print(f"  L=16384 projective steps: {1e3 * (t1 - t0):.0f} ms, {1e3 * (t2 - t1):.0f} ms", flush=True)
+    ev = sim.pm_events()
+    col = _ring_generating_column(L, 1.0, dt)
+    for t in range(2):
+        u_sel, u_out = pm_uniforms(seed, t, 2, L)
+        q = min(gams[t] * dt, 1.0)
+        sites = [e[0] for e in ev[t]]
+        assert sites == [j for j in range(L) if u_sel[j] < q]
+        for j, p, o in ev[t]:
+            assert o == (1 if u_out[j] <= p else 0)
+            assert -1e-12 <= p <= 1.0 + 1e-12
+        # conditional probabilities of the first six sites
+        M = np.array(sites[:6])
+        Prow = col[(M[:, None] - np.arange(L)[None, :]) % L]
+        Y = Prow @ U1[t]
+        C = Y @ Y.conj().T
+        tols = prob_tols(ev[t][:6])
+        for s, (j, p, o) in enumerate(ev[t][:6]):
+            p_ref = C[s, s].real
+            assert abs(p - p_ref) <= tols[s], (t, s, p, p_ref)
+            C = project_outcome1(C, s) if o == 1 else project_outcome0(C, s)
+    del U1
+    U2, _ = sim.get_state()
+    rng = np.random.default_rng(5)
+    cols = rng.choice(N, 8, replace=False)
+    for t in range(2):
+        G = U2[t].conj().T @ U2[t][:, cols]
+        E = np.zeros((N, len(cols)))
+        E[cols, np.arange(len(cols))] = 1.0
+        assert np.abs(G - E).max() <= 1e-10
+    del U2
+    p = sim.occupations()
+    for l in (1024, 8192):
+        A = list(range(l))
+        lam = sim.region_spectrum(A)
+        for t in range(2):
+            assert lam[t].min() >= -1e-10 and lam[t].max() <= 1.0 + 1e-10
+            assert abs(lam[t].sum() - p[t, :l].sum()) <= 1e-8
+    sim.close()
