@@ -137,6 +137,68 @@ def summarize_pmc(fetch_csv, write_csv, out_path):
     print(json.dumps(d))
 
 
+def run_large(args):
+    """The large single-trajectory shapes (one trajectory per gamma, batched): `steps` timed
+    steps after `warmup`, per-phase times, then every observation of the workload timed on
+    its own (S of each region, or the mutual information of the two strips)."""
+    import numpy as np
+    import torch
+    from paper_2508_18468_amd import mfq
+    from paper_2508_18468_amd.workloads import ring_pm_large, torus_qsd
+    w = ring_pm_large() if args.workload == "ring16384_pm" else torus_qsd()
+    prec_name = args.precision or ("fp64" if w.dim == 1 else "fp32_bulk")
+    precision = mfq.FP64 if prec_name == "fp64" else mfq.FP32_BULK
+    B = len(w.gammas)
+    uids = [g * w.n_traj for g in range(B)]
+    sim = mfq.Trajectories(w.dim, w.Lx, w.Ly, n_traj=B, uids=uids, device=0, precision=precision)
+    gam = np.asarray(w.gammas, dtype=np.float64)
+    steps = min(args.steps, 8)
+    warm = min(args.warmup, 2)
+    print(f"{w.name}: L={w.L} N={w.N} trajectories={B} {prec_name}: {warm} warm-up steps",
+          file=sys.stderr, flush=True)
+    sim.step(w.protocol, gam, w.dt, w.seed, warm)
+    sim.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.step(w.protocol, gam, w.dt, w.seed, 1)
+        sim.synchronize()
+        print(f"  step {k + 1}/{steps} done", file=sys.stderr, flush=True)
+    T = time.perf_counter() - t0
+    phases = sim.phase_times()
+    sim.profile(False)
+    obs = {}
+    if w.mi:
+        A, Bs = w.mi
+        t1 = time.perf_counter()
+        I2 = sim.mutual_info(A, Bs)
+        obs["mutual_info_s"] = time.perf_counter() - t1
+        obs["I2"] = [float(x) for x in I2]
+    for r in w.regions:
+        t1 = time.perf_counter()
+        S = sim.entropy(r)
+        obs[f"S_l{len(r)}_s"] = time.perf_counter() - t1
+        obs[f"S_l{len(r)}"] = [float(x) for x in S]
+    sim.close()
+    prop_ms, prop_n = phases["propagate"]
+    flops = 8.0 * w.L * w.L * w.N * B
+    tf = flops / (prop_ms / prop_n * 1e-3) / 1e12 if prop_n else None
+    peak = PEAK_FP64_TFLOPS if precision == mfq.FP64 else PEAK_FP32_TFLOPS
+    out = {"metric": "L*N*steps/s", "value": B * w.L * w.N * steps / T, "unit": "L*N*steps/s",
+           "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": T / steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if precision == mfq.FP64 else "f64 (propagator f32)", "data": "synthetic",
+           "config": {"workload": w.name, "L": w.L, "N": w.N, "n_traj": B,
+                      "gammas": list(w.gammas), "protocol": "projective" if w.protocol == 0 else "homodyne",
+                      "dt": w.dt, "precision": prec_name},
+           "roofline": {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                        "frac": tf / peak if tf else None, "traffic": None,
+                        "kernel": "propagator", "algorithmic_flops_per_launch": flops},
+           "phase_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
+           "observations": obs}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +209,13 @@ def main():
     ap.add_argument("--pmc-workload", action="store_true",
                     help="short run for rocprofv3 --pmc passes (3 steps + calibration copy)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
+    ap.add_argument("--workload", default="ring1024_qsd",
+                    choices=["ring1024_qsd", "ring16384_pm", "torus160_qsd"],
+                    help="ring1024_qsd (default) is the benchmark line; the two large single-"
+                         "trajectory shapes time a few steps and their observations")
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32_bulk"],
+                    help="large workloads only (default: fp64 for the ring, fp32_bulk propagator "
+                         "for the torus)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
@@ -158,6 +227,10 @@ def main():
         print("bench.py runs on one GPU only: trajectories shard across GPUs with no communication, "
               "so the multi-GPU figure is n_gpus x the one-GPU value; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload != "ring1024_qsd":
+        run_large(args)
+        return
 
     import numpy as np
     import torch

@@ -197,6 +197,38 @@ mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double d
 #define MFQ_PM_BLOCKED 2
 mfq_status mfq_set_pm_path(mfq_ctx *ctx, int32_t path);
 
+/* GEMM tile choice of a context (all its contractions, the propagator included). */
+#define MFQ_TILE_AUTO 0   /* 128 x 128 tiles for large contractions, 64 x 64 otherwise */
+#define MFQ_TILE_SMALL 1  /* always 64 x 64 (4 waves) */
+#define MFQ_TILE_LARGE 2  /* 128 x 128 (8 waves) whenever every dimension is >= 128 */
+
+/* Result of mfq_autotune. */
+typedef struct {
+  int32_t path;             /* chosen mfq_run path: MFQ_PATH_FUSED or MFQ_PATH_LAUNCHES */
+  int32_t tile;             /* chosen MFQ_TILE_* */
+  double ms_per_step;       /* wall time per step of the chosen configuration */
+  int32_t n_candidates;     /* entries used in candidate_ms */
+  int32_t reserved;
+  double candidate_ms[8];   /* ms per step of: launches x {AUTO, SMALL, LARGE}, then fused (if
+                               the problem fits in LDS) */
+} mfq_tuning;
+
+/* Autotuner of the execution form of a step (the batched launch of the hot
+ * path): times probe_steps steps of the given protocol and parameters under
+ * every candidate (per-phase launches with each GEMM tile choice, and the fused
+ * LDS-resident kernel when the problem fits), each after one warm-up run, and
+ * keeps the fastest as the context's path (for mfq_run) and tile choice (for
+ * every call).  The state, the step index and the events of the last step are
+ * saved before and restored after the probes, so tuning does not change any
+ * trajectory.  Allocates a temporary device copy of the state.  Synchronises.
+ * Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_ENOMEM / MFQ_EDEVICE, or the first error a
+ * probe reports (the previous choice is then kept). */
+mfq_status mfq_autotune(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                        int32_t probe_steps, mfq_tuning *out);
+
+/* Apply a previously tuned choice (e.g. from a cache) without probing. */
+mfq_status mfq_set_tuning(mfq_ctx *ctx, int32_t path, int32_t tile);
+
 #define MFQ_PATH_AUTO 0     /* fused when the problem fits in LDS, else per-phase kernels */
 #define MFQ_PATH_FUSED 1    /* force the fused single-launch path (MFQ_EINVAL if it does not fit) */
 #define MFQ_PATH_LAUNCHES 2 /* force the per-phase kernels */

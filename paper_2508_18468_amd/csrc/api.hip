@@ -2,6 +2,7 @@
 // drivers.  Every arithmetic step runs in the HIP kernels of this library;
 // the host only validates arguments, computes the propagator's generating
 // row (a Bessel series, once per dt) and orders launches on the stream.
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -60,8 +61,10 @@ struct mfq_ctx {
   int g_protocol = -1, g_cur = -1;
   double g_dt = NAN;
   uint64_t g_seed = 0;
-  // mfq_run: execution path and its observation buffer
-  int run_path = 0;  // MFQ_PATH_AUTO
+  // mfq_run: execution path and its observation buffer; GEMM tile choice
+  int run_path = 0;   // MFQ_PATH_AUTO
+  int tile_mode = 0;  // MFQ_TILE_AUTO
+  int g_tile = -1;    // tile choice the cached graph was captured with
   double *run_S = nullptr;
   size_t run_S_cap = 0;
 };
@@ -383,6 +386,13 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
   return MFQ_OK;
 }
 
+// The context's GEMM tile choice for the launches of one ABI call.
+struct TileScope {
+  int saved;
+  explicit TileScope(const mfq_ctx *c) : saved(gemm_tile_mode()) { set_gemm_tile_mode(c->tile_mode); }
+  ~TileScope() { set_gemm_tile_mode(saved); }
+};
+
 void drop_graph(mfq_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -394,7 +404,8 @@ void drop_graph(mfq_ctx *c) {
 // plus the step-counter advance; rebuilt when protocol, dt, seed or buffer
 // parity change.  Replayed with hipGraphLaunch for each pair of steps.
 mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed) {
-  if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur)
+  if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur &&
+      c->g_tile == c->tile_mode)
     return MFQ_OK;
   drop_graph(c);
   const int cur0 = c->cur;
@@ -417,6 +428,7 @@ mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed)
   c->g_dt = dt;
   c->g_seed = seed;
   c->g_cur = cur0;
+  c->g_tile = c->tile_mode;
   return MFQ_OK;
 }
 
@@ -555,6 +567,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
 mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                     int32_t n_steps) {
   if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
   mfq_status sv = validate_step(c, protocol, gamma, dt, n_steps);
   if (sv) return sv;
   if (n_steps == 0) return MFQ_OK;
@@ -597,6 +610,7 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out) {
   if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
   mfq_status st = validate_step(c, protocol, gamma, dt, n_steps);
   if (st) return st;
   if (obs_every < 0) return fail(c, MFQ_EINVAL, "obs_every < 0");
@@ -661,6 +675,109 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   return check_flag(c);
 }
 
+mfq_status mfq_set_tuning(mfq_ctx *c, int32_t path, int32_t tile) {
+  if (!c) return MFQ_EINVAL;
+  if (path != MFQ_PATH_AUTO && path != MFQ_PATH_FUSED && path != MFQ_PATH_LAUNCHES)
+    return fail(c, MFQ_EINVAL, "unknown path");
+  if (tile != MFQ_TILE_AUTO && tile != MFQ_TILE_SMALL && tile != MFQ_TILE_LARGE)
+    return fail(c, MFQ_EINVAL, "unknown tile choice");
+  c->run_path = path;
+  c->tile_mode = tile;
+  drop_graph(c);
+  return MFQ_OK;
+}
+
+mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
+                        int32_t probe_steps, mfq_tuning *out) {
+  if (!c) return MFQ_EINVAL;
+  if (!out) return fail(c, MFQ_EINVAL, "out is NULL");
+  mfq_status st = validate_step(c, protocol, gamma, dt, probe_steps);
+  if (st) return st;
+  if (probe_steps < 1 || probe_steps > 1000) return fail(c, MFQ_EINVAL, "need 1 <= probe_steps <= 1000");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  // the state and the events of the last step are saved and restored around the probes
+  const size_t ubytes = (size_t)c->L * c->N * c->B * sizeof(cplx);
+  const size_t ev = (size_t)c->L * c->B;
+  const size_t ebytes = ev * (2 * sizeof(int) + sizeof(double)) + c->B * sizeof(int);
+  char *save = nullptr;
+  HIPCHK(hipMalloc(&save, ubytes + ebytes), "autotune save buffer");
+  auto copy_events = [&](bool to_save) -> hipError_t {
+    char *p = save + ubytes;
+    struct Piece { void *dev; size_t n; } pieces[4] = {{c->pm_sites, ev * sizeof(int)},
+                                                        {c->pm_out, ev * sizeof(int)},
+                                                        {c->pm_prob, ev * sizeof(double)},
+                                                        {c->pm_cnt, c->B * sizeof(int)}};
+    for (const Piece &q : pieces) {
+      hipError_t e = to_save ? hipMemcpyAsync(p, q.dev, q.n, hipMemcpyDeviceToDevice, c->stream)
+                             : hipMemcpyAsync(q.dev, p, q.n, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return e;
+      p += q.n;
+    }
+    return hipSuccess;
+  };
+  const int cur0 = c->cur;
+  const int64_t step0 = c->step;
+  const int path0 = c->run_path, tile0 = c->tile_mode;
+  hipError_t he = hipMemcpyAsync(save, c->X[cur0], ubytes, hipMemcpyDeviceToDevice, c->stream);
+  if (he == hipSuccess) he = copy_events(true);
+  auto restore = [&]() -> hipError_t {
+    c->cur = cur0;
+    c->step = step0;
+    hipError_t e = hipMemcpyAsync(c->X[cur0], save, ubytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+  };
+  struct Cand { int path, tile; };
+  std::vector<Cand> cands = {{MFQ_PATH_LAUNCHES, MFQ_TILE_AUTO},
+                             {MFQ_PATH_LAUNCHES, MFQ_TILE_SMALL},
+                             {MFQ_PATH_LAUNCHES, MFQ_TILE_LARGE}};
+  const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+  if (fused_fits(c->L, c->N, c->lat.Lx, Ly)) cands.push_back({MFQ_PATH_FUSED, MFQ_TILE_AUTO});
+  std::memset(out, 0, sizeof(*out));
+  int best = -1;
+  double best_ms = 0.0;
+  for (size_t i = 0; i < cands.size() && he == hipSuccess && st == MFQ_OK; ++i) {
+    c->run_path = cands[i].path;
+    c->tile_mode = cands[i].tile;
+    double ms = 0.0;
+    for (int rep = 0; rep < 2 && he == hipSuccess && st == MFQ_OK; ++rep) {  // warm-up, then timed
+      if ((he = restore()) != hipSuccess) break;
+      int32_t n_obs = 0;
+      const auto t0 = std::chrono::steady_clock::now();
+      st = mfq_run(c, protocol, gamma, dt, seed, probe_steps, 0, nullptr, 0, nullptr, &n_obs);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    out->candidate_ms[i] = ms / probe_steps;
+    if (st == MFQ_OK && (best < 0 || ms < best_ms)) {
+      best = (int)i;
+      best_ms = ms;
+    }
+  }
+  out->n_candidates = (int32_t)cands.size();
+  const std::string probe_err = c->err;
+  if (he == hipSuccess) he = restore();
+  if (he == hipSuccess) he = copy_events(false);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  (void)hipFree(save);
+  drop_graph(c);
+  if (he != hipSuccess) {
+    c->run_path = path0;
+    c->tile_mode = tile0;
+    return hip_fail(c, he, "autotune");
+  }
+  if (st != MFQ_OK || best < 0) {
+    c->run_path = path0;
+    c->tile_mode = tile0;
+    return fail(c, st ? st : MFQ_EDEVICE, "autotune probe failed: " + probe_err);
+  }
+  c->run_path = cands[best].path;
+  c->tile_mode = cands[best].tile;
+  out->path = c->run_path;
+  out->tile = c->tile_mode;
+  out->ms_per_step = best_ms / probe_steps;
+  return MFQ_OK;
+}
+
 mfq_status mfq_reset_trajectory(mfq_ctx *c, int32_t slot, uint64_t uid) {
   if (!c) return MFQ_EINVAL;
   if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
@@ -680,6 +797,7 @@ mfq_status mfq_use_graphs(mfq_ctx *c, int32_t enable) {
 
 mfq_status mfq_entropy(mfq_ctx *c, const int32_t *region, int32_t n_sites, double *S_host) {
   if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
   if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
   if (!S_host) return fail(c, MFQ_EINVAL, "S_host is NULL");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
@@ -690,6 +808,7 @@ mfq_status mfq_entropy(mfq_ctx *c, const int32_t *region, int32_t n_sites, doubl
 
 mfq_status mfq_region_spectrum(mfq_ctx *c, const int32_t *region, int32_t n_sites, double *lam_host) {
   if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
   if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
   if (!lam_host) return fail(c, MFQ_EINVAL, "lam_host is NULL");
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
@@ -706,6 +825,7 @@ mfq_status mfq_region_spectrum(mfq_ctx *c, const int32_t *region, int32_t n_site
 mfq_status mfq_mutual_info(mfq_ctx *c, const int32_t *A, int32_t nA, const int32_t *B, int32_t nB,
                            double *I_host) {
   if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
   if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
   if (!I_host) return fail(c, MFQ_EINVAL, "I_host is NULL");
   mfq_status st = validate_region(c, A, nA);

@@ -20,6 +20,12 @@ constexpr int NB = CHOL_NB;
 // Factorise the w x w diagonal block at (c0, c0) of G[b] (upper triangle),
 // write R_JJ back into G and R_JJ^{-1} (full block, zeros below the diagonal)
 // into Rinv[b].  A non-positive or non-finite pivot raises *flag.
+//
+// The elimination runs without square roots: step k subtracts
+// conj(G_ki) G_kj / G_kk from the trailing upper triangle, one barrier per
+// step, each thread owning a fixed 4 x 4 set of (row, column) positions; the
+// rows of R are scaled by 1/sqrt(G_kk) afterwards.  The inverse is formed by
+// back substitution with four lanes per column.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, int N, int c0, int w,
                                                          int *flag, const double *skip_if_le,
                                                          double skip_thr) {
@@ -29,101 +35,78 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
   cplx *Rb = Rinv + (long)b * N * N;
   __shared__ cplx a[NB][NB + 1];  // a[c][r] = element (row r, col c) of the block
   __shared__ cplx x[NB][NB + 1];  // x[c][r] = element (r, c) of the inverse
+  __shared__ double rs[NB];       // sqrt of the pivots
   __shared__ int bad;
   if (tid == 0) bad = 0;
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int r = idx % w, c = idx / w;
-    a[c][r] = (r <= c) ? Gb[(c0 + r) + (long)(c0 + c) * N] : cplx{0.0, 0.0};
+  for (int c = tid >> 6; c < w; c += 4)
+    for (int r = tid & 63; r < w; r += 64)
+      a[c][r] = (r <= c) ? Gb[(c0 + r) + (long)(c0 + c) * N] : cplx{0.0, 0.0};
+  __syncthreads();
+  const int ti = tid & 15, tj = tid >> 4;  // rows ti + 16 p, columns tj + 16 q
+  for (int k = 0; k + 1 < w; ++k) {
+    double d = a[k][k].re;
+    if (!(d > 0.0) || !isfinite(d)) d = 1.0;  // flagged below
+    const double inv = 1.0 / d;
+#pragma unroll
+    for (int q = 0; q < NB / 16; ++q) {
+      const int j = tj + 16 * q;
+      if (j <= k || j >= w) continue;
+      const cplx gkj = a[j][k];
+      const double fr = gkj.re * inv, fi = gkj.im * inv;
+#pragma unroll
+      for (int p = 0; p < NB / 16; ++p) {
+        const int i = ti + 16 * p;
+        if (i <= k || i > j) continue;
+        const cplx gki = a[i][k];  // a[j][i] -= conj(G_ki) G_kj / G_kk
+        a[j][i].re -= gki.re * fr + gki.im * fi;
+        a[j][i].im -= gki.re * fi - gki.im * fr;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < w) {
+    const double d = a[tid][tid].re;
+    if (!(d > 0.0) || !isfinite(d)) {
+      bad = 1;
+      rs[tid] = 1.0;
+    } else {
+      rs[tid] = sqrt(d);
+    }
   }
   __syncthreads();
-  for (int k = 0; k < w; ++k) {
-    if (tid == 0) {
-      double d = a[k][k].re;
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
-      }
-      a[k][k] = cplx{sqrt(d), 0.0};
+  for (int c = tid >> 6; c < w; c += 4)
+    for (int r = tid & 63; r <= c; r += 64) {
+      const double sc = 1.0 / rs[r];
+      a[c][r] = r == c ? cplx{rs[r], 0.0} : cplx{a[c][r].re * sc, a[c][r].im * sc};
     }
-    __syncthreads();
-    const double rkk = a[k][k].re;
-    for (int j = k + 1 + tid; j < w; j += 256) {
-      a[j][k].re /= rkk;
-      a[j][k].im /= rkk;
-    }
-    __syncthreads();
-    // trailing: a(i, j) -= conj(R_ki) R_kj for k < i <= j < w
-    const int m = w - k - 1;
-    for (int idx = tid; idx < m * m; idx += 256) {
-      const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i > j) continue;
-      const cplx rki = a[i][k], rkj = a[j][k];
-      a[j][i].re -= rki.re * rkj.re + rki.im * rkj.im;
-      a[j][i].im -= rki.re * rkj.im - rki.im * rkj.re;
-    }
-    __syncthreads();
-  }
-  // inverse of the upper triangular block by back substitution, one column per thread
-  if (tid < w) {
-    const int j = tid;
-    for (int i = w - 1; i > j; --i) x[j][i] = cplx{0.0, 0.0};
+  __syncthreads();
+  // inverse of the upper triangular block: column j by lanes 4j .. 4j+3
+  const int j = tid >> 2, q = tid & 3;
+  if (j < w) {
+    for (int i = j + 1 + q; i < w; i += 4) x[j][i] = cplx{0.0, 0.0};
     x[j][j] = cplx{1.0 / a[j][j].re, 0.0};
     for (int i = j - 1; i >= 0; --i) {
       double sr = 0.0, si = 0.0;
-      for (int k = i + 1; k <= j; ++k) {
-        const cplx r = a[k][i], t = x[j][k];
+      for (int l = i + 1 + q; l <= j; l += 4) {
+        const cplx r = a[l][i], t = x[j][l];
         sr += r.re * t.re - r.im * t.im;
         si += r.re * t.im + r.im * t.re;
       }
+      sr += __shfl_xor(sr, 1, 64);
+      si += __shfl_xor(si, 1, 64);
+      sr += __shfl_xor(sr, 2, 64);
+      si += __shfl_xor(si, 2, 64);
       const double inv = 1.0 / a[i][i].re;
-      x[j][i] = cplx{-sr * inv, -si * inv};
+      x[j][i] = cplx{-sr * inv, -si * inv};  // the four lanes store the same value
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < w * w; idx += 256) {
-    const int r = idx % w, c = idx / w;
-    if (r <= c) Gb[(c0 + r) + (long)(c0 + c) * N] = a[c][r];
-    Rb[(c0 + r) + (long)(c0 + c) * N] = x[c][r];
-  }
+  for (int c = tid >> 6; c < w; c += 4)
+    for (int r = tid & 63; r < w; r += 64) {
+      if (r <= c) Gb[(c0 + r) + (long)(c0 + c) * N] = a[c][r];
+      Rb[(c0 + r) + (long)(c0 + c) * N] = x[c][r];
+    }
   if (tid == 0 && bad) atomicOr(flag, 1);
-}
-
-// E = G - I over the upper triangle of every Gram: writes the first-order
-// inverse factor R^{-1} = I - triu(E, 1) - diag(E)/2 and raises *maxdev to the
-// largest |E_ij| (non-negative doubles order like their bit patterns; a NaN
-// compares above every finite value and so selects the full factorisation).
-__global__ __launch_bounds__(256) void near_identity_kernel(const cplx *G, cplx *Rinv, int N,
-                                                            double *maxdev) {
-  const int c = blockIdx.x, b = blockIdx.y;  // one column of one Gram per workgroup
-  const long NN = (long)N * N;
-  const cplx *Gc = G + b * NN + (long)c * N;
-  cplx *Rc = Rinv + b * NN + (long)c * N;
-  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
-  double m = 0.0;
-  for (int r = threadIdx.x; r < N; r += 256) {
-    cplx out{0.0, 0.0};
-    if (r <= c) {
-      const cplx e = Gc[r];
-      const double d = (r == c) ? e.re - 1.0 : e.re;
-      const double a = fabs(d) + fabs(e.im);
-      m = (!(a <= 1e300) || m != m) ? qnan : fmax(m, a);
-      out = (r == c) ? cplx{1.0 - 0.5 * d, 0.0} : cplx{-e.re, -e.im};
-    }
-    Rc[r] = out;
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const double x = red[threadIdx.x], y = red[threadIdx.x + o];
-      red[threadIdx.x] = (x != x || y != y) ? qnan : fmax(x, y);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0)
-    atomicMax(reinterpret_cast<unsigned long long *>(maxdev),
-              (unsigned long long)__double_as_longlong(red[0]));
 }
 
 GemmDesc desc() {
@@ -143,7 +126,9 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
   // test passed (max |E| <= threshold)
   const double *skip = near_identity ? wk.dev : nullptr;
   const double thr = CHOL_FIRST_ORDER_MAX;
-  // G = Uin^+ Uin (upper triangle)
+  // G = Uin^+ Uin (upper triangle); with near_identity the Gram's epilogue also
+  // writes the first-order factor into Rinv and the largest |G - I| into wk.dev
+  if (near_identity && (e = fill_zero(wk.dev, sizeof(double), s)) != hipSuccess) return e;
   {
     GemmDesc g = desc();
     g.M = N; g.N = N; g.K = L; g.batch = B;
@@ -151,12 +136,11 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     g.B = Uin; g.ldb = L; g.sB = (long)L * N; g.opB = OP_N;
     g.D = wk.G; g.ldd = N; g.sD = NN;
     g.tri = TRI_UPPER;
+    if (near_identity) {
+      g.R1 = wk.Rinv;
+      g.maxdev = wk.dev;
+    }
     if ((e = zgemm(g, s)) != hipSuccess) return e;
-  }
-  if (near_identity) {
-    if ((e = fill_zero(wk.dev, sizeof(double), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(near_identity_kernel, dim3(N, B), dim3(256), 0, s, wk.G, wk.Rinv, N, wk.dev);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int nJ = (N + NB - 1) / NB;
   for (int J = 0; J < nJ; ++J) {

@@ -2,9 +2,11 @@
 // lattices, sizes and protocols by device-memory footprint and advances them
 // with continuous batching (engine_policy.h).  A worker thread owns the GPU
 // work: every batch group is one library context with its own stream, so the
-// groups' steps overlap on the device; each group advances in chunks of
-// about CHUNK_TARGET_S of wall time, up to the next observation or completion
-// of one of its jobs, after which finished slots are refilled from the queue.
+// groups' steps overlap on the device.  Each round advances the groups whose
+// next job completion is nearest in work (shortest first, up to a combined
+// width that occupies the device), each in chunks of about CHUNK_TARGET_S of
+// wall time, up to the next observation or completion of one of its jobs,
+// after which finished slots are refilled from the queue.
 // Each job keeps its own random numbers (key = (seed, uid), counter = its own
 // step index), so a job gives the same result alone and in any mix.
 #include <chrono>
@@ -21,6 +23,9 @@ using namespace mfq_serving;
 namespace {
 constexpr double CHUNK_TARGET_S = 0.02;
 constexpr int CHUNK_MAX = 64;
+// Groups advanced together hold at least this many state elements (L * N per
+// trajectory): 128 x 128-tile propagator products of ~2000 workgroups.
+constexpr double WIDTH_BUDGET = 32.0 * 1024 * 1024;
 }
 
 struct mfq_engine {
@@ -100,7 +105,7 @@ void worker_loop(mfq_engine *e) {
     std::vector<int> active;
     {
       std::unique_lock<std::mutex> lk(e->m);
-      active = e->policy.active_groups();
+      active = e->policy.schedule(WIDTH_BUDGET);
       if (active.empty()) {
         e->cv.wait_for(lk, std::chrono::milliseconds(5));
         continue;

@@ -252,6 +252,43 @@ class Policy {
       if (g.alive && g.created && g.active() > 0) v.push_back(g.id);
     return v;
   }
+
+  // Work left for the job of group gid that will finish first, in flops at about
+  // 8 L^3 per trajectory-step for N = L/2 (propagator 8 L^2 N, two Cholesky-QR
+  // passes 16 L N^2).
+  double next_completion_work(int gid) const {
+    const Group &g = groups_[gid];
+    const double L = (double)g.key.Lx * g.key.Ly, N = g.key.N;
+    double best = -1.0;
+    for (int64_t jid : g.slot_job) {
+      if (jid < 0) continue;
+      const Job &j = jobs_.at((uint64_t)jid);
+      const double w = (double)(j.n_steps - j.steps_done) * (8.0 * L * L * N + 16.0 * L * N * N);
+      if (best < 0.0 || w < best) best = w;
+    }
+    return best;
+  }
+
+  // Groups to advance now: active groups in order of the work left to their next
+  // job completion (shortest first), taken until their combined width (trajectory
+  // elements L * N * slots) reaches width_budget; at least one group.  Running the
+  // shortest work first lowers the median latency of an overloaded queue, and the
+  // width budget keeps enough groups in flight to occupy the device.
+  std::vector<int> schedule(double width_budget) const {
+    std::vector<int> act = active_groups();
+    std::vector<std::pair<double, int>> order;
+    for (int gid : act) order.push_back({next_completion_work(gid), gid});
+    std::sort(order.begin(), order.end());
+    std::vector<int> out;
+    double width = 0.0;
+    for (const auto &o : order) {
+      if (!out.empty() && width >= width_budget) break;
+      const Group &g = groups_[o.second];
+      width += (double)g.key.Lx * g.key.Ly * g.key.N * g.capacity;
+      out.push_back(o.second);
+    }
+    return out;
+  }
   int live_groups() const {
     int n = 0;
     for (const Group &g : groups_) n += g.alive ? 1 : 0;

@@ -26,14 +26,27 @@ struct GemmDesc {
   cplx *D; long ldd, sD;
   cplx alpha, beta;        // beta == 0 -> Cin is not read
   int tri;                 // TRI_UPPER: only tiles touching the upper triangle of D
-  int aUpper;              // op(A) is upper triangular: A[m][k] = 0 for k < m
-  int bUpper;              // op(B) is upper triangular: B[k][n] = 0 for k > n
+  int aUpper;              // op(A) is upper triangular: A[m][k] taken as 0 for k < m (not read)
+  int bUpper;              // op(B) is upper triangular: B[k][n] taken as 0 for k > n (not read)
   const double *skip_if_le;  // if set and *skip_if_le <= skip_thr, the launch does nothing
   double skip_thr;
   long sIdxA, sIdxB;       // batch stride of idxA / idxB (0: one index list for all entries)
+  // Near-identity epilogue of an upper Gram (square, TRI_UPPER, alpha = 1, beta = 0): with
+  // E = D - I, also writes the upper triangle of R1 = I - triu(E, 1) - diag(E)/2 (ld and
+  // batch stride as D) and raises *maxdev to max |Re E|+|Im E| (a NaN or an infinity
+  // raises it to NaN).  *maxdev must be zeroed beforehand.
+  cplx *R1;
+  double *maxdev;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
+// Tile choice for the GEMMs launched by the calling thread: AUTO (64 x 64 unless every
+// dimension is >= 128 and the work fills the chip), SMALL (always 64 x 64, the propagator
+// included), LARGE (128 x 128 whenever every dimension is >= 128).  Set by the context
+// around its launches from its tuned choice.
+enum { GEMM_TILE_AUTO = 0, GEMM_TILE_SMALL = 1, GEMM_TILE_LARGE = 2 };
+void set_gemm_tile_mode(int mode);
+int gemm_tile_mode();
 // Same contraction (op N, op N), launched under a distinct kernel name.
 hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s);
 

@@ -133,7 +133,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPA == OP_N ? a_slow + DA * i : a_fast;
       const int gm = m0 + m, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if (!EDGE || (gm < g.M && gk < kend)) {
+      if ((!EDGE || (gm < g.M && gk < kend)) && !(g.aUpper && gk < gm)) {
         cplx v;
         if (OPA == OP_N) {
           const long row = idxA ? idxA[gm] : gm;
@@ -153,7 +153,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPB == OP_N ? b_fast : b_slow + DB * i;
       const int gn = n0 + n, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if (!EDGE || (gn < g.N && gk < kend)) {
+      if ((!EDGE || (gn < g.N && gk < kend)) && !(g.bUpper && gk > gn)) {
         cplx v;
         if (OPB == OP_N) {
           const long row = idxB ? idxB[gk] : gk;
@@ -244,6 +244,9 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   const bool useC = (g.beta.re != 0.0 || g.beta.im != 0.0);
   const cplx *Cin = g.Cin ? g.Cin + (long)b * g.sCin : nullptr;
   cplx *D = g.D + (long)b * g.sD;
+  cplx *R1 = g.R1 ? g.R1 + (long)b * g.sD : nullptr;
+  double dmax = 0.0;
+  const double qnan = __longlong_as_double(0x7ff8000000000000ll);
 #pragma unroll
   for (int i = 0; i < IM; ++i)
 #pragma unroll
@@ -263,7 +266,22 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
           yi += g.beta.re * c.im + g.beta.im * c.re;
         }
         D[row + (long)col * g.ldd] = cplx{yr, yi};
+        if (R1) {
+          const double er = row == col ? yr - 1.0 : yr;
+          const double a = fabs(er) + fabs(yi);
+          dmax = (!(a <= 1e300) || dmax != dmax) ? qnan : fmax(dmax, a);
+          R1[row + (long)col * g.ldd] = row == col ? cplx{1.0 - 0.5 * er, 0.0} : cplx{-yr, -yi};
+        }
       }
+  if (R1) {  // non-negative doubles order like their bit patterns; NaN is above them all
+    for (int o = 32; o > 0; o >>= 1) {
+      const double y = __shfl_xor(dmax, o, 64);
+      dmax = (y != y || dmax != dmax) ? qnan : fmax(dmax, y);
+    }
+    if (lane == 0)
+      atomicMax(reinterpret_cast<unsigned long long *>(g.maxdev),
+                (unsigned long long)__double_as_longlong(dmax));
+  }
 }
 
 template <int MT>
@@ -276,12 +294,19 @@ __global__ __launch_bounds__(nthreads<NT>()) void zgemm_kernel(GemmDesc g) {
   zgemm_body<OPA, OPB, MT, NT, kchunk<MT>(), GATHER, EDGE>(g);
 }
 
-// The propagator product U <- P U gets its own symbol so that profilers can
+// The propagator product U <- P U gets its own symbols so that profilers can
 // tell it apart from the other contractions of a step.
 template <bool EDGE>
 __global__ __launch_bounds__(512) void propagator_zgemm_kernel(GemmDesc g) {
   zgemm_body<OP_N, OP_N, 128, 128, kchunk<128>(), false, EDGE>(g);
 }
+template <bool EDGE>
+__global__ __launch_bounds__(256) void propagator_zgemm_kernel_t64(GemmDesc g) {
+  zgemm_body<OP_N, OP_N, 64, 64, kchunk<64>(), false, EDGE>(g);
+}
+
+// Tile choice of the calling thread (see set_gemm_tile_mode).
+thread_local int tl_tile_mode = GEMM_TILE_AUTO;
 
 template <int MT, int NT>
 unsigned grid_size(const GemmDesc &g) {
@@ -321,8 +346,17 @@ hipError_t launch(const GemmDesc &g, hipStream_t s) {
 
 }  // namespace
 
+void set_gemm_tile_mode(int mode) { tl_tile_mode = mode; }
+int gemm_tile_mode() { return tl_tile_mode; }
+
 hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  if (tl_tile_mode == GEMM_TILE_SMALL) {
+    const dim3 grid(grid_size<64, 64>(g));
+    if (needs_edge<64, 64>(g)) hipLaunchKernelGGL(propagator_zgemm_kernel_t64<true>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(propagator_zgemm_kernel_t64<false>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   const dim3 grid(grid_size<128, 128>(g));
   if (needs_edge<128, 128>(g)) hipLaunchKernelGGL(propagator_zgemm_kernel<true>, grid, dim3(512), 0, s, g);
   else hipLaunchKernelGGL(propagator_zgemm_kernel<false>, grid, dim3(512), 0, s, g);
@@ -331,9 +365,13 @@ hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s) {
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  // Large tiles only when every dimension fills them and there is enough work.
+  if (tl_tile_mode == GEMM_TILE_SMALL) return launch<64, 64>(g, s);
+  // Large tiles only when every dimension fills them (and, by default, when there is
+  // enough work to occupy the chip with them).
   const long work = (long)g.M * g.N * g.batch;
-  if (g.M >= 128 && g.N >= 128 && g.K >= 128 && work >= (1L << 22)) return launch<128, 128>(g, s);
+  if (g.M >= 128 && g.N >= 128 && g.K >= 128 &&
+      (tl_tile_mode == GEMM_TILE_LARGE || work >= (1L << 22)))
+    return launch<128, 128>(g, s);
   return launch<64, 64>(g, s);
 }
 

@@ -41,6 +41,12 @@ class Job(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("uid", ctypes.c_uint64), ("region", ctypes.c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+                ("n_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("candidate_ms", ctypes.c_double * 8)]
+
+
 class EngineStats(ctypes.Structure):
     _fields_ = [("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("budget_bytes", ctypes.c_uint64), ("queued", ctypes.c_int64), ("groups", ctypes.c_int32),
@@ -79,6 +85,9 @@ _SIGS = {
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_set_pm_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
+    "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mfq_reset_trajectory": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
     "mfq_engine_create": (ctypes.c_int32, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_void_p)]),
@@ -239,6 +248,24 @@ def mfq_reset_trajectory(ctx, slot, uid):
     _check(ctx, lib().mfq_reset_trajectory(ctx, int(slot), int(uid)))
 
 
+TILE_AUTO, TILE_SMALL, TILE_LARGE = 0, 1, 2
+TUNE_CANDIDATES = [("launches", TILE_AUTO), ("launches", TILE_SMALL), ("launches", TILE_LARGE),
+                   ("fused", TILE_AUTO)]
+
+
+def mfq_autotune(ctx, protocol, gamma, dt, seed, probe_steps):
+    g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    t = Tuning()
+    _check(ctx, lib().mfq_autotune(ctx, int(protocol), _ptr(g), float(dt), int(seed), int(probe_steps),
+                                   ctypes.byref(t)))
+    return {"path": t.path, "tile": t.tile, "ms_per_step": t.ms_per_step,
+            "candidate_ms": [t.candidate_ms[i] for i in range(t.n_candidates)]}
+
+
+def mfq_set_tuning(ctx, path, tile):
+    _check(ctx, lib().mfq_set_tuning(ctx, int(path), int(tile)))
+
+
 PM_AUTO, PM_WORKGROUP, PM_BLOCKED = 0, 1, 2
 
 
@@ -342,6 +369,7 @@ class Trajectories:
         self.L = Lx * (Ly if dim == 2 else 1)
         self.N = self.L // 2 if N is None else N
         self.n_traj = n_traj
+        self.precision = precision
         self.uids = list(range(n_traj)) if uids is None else list(uids)
         self.device = device
         torch.cuda.set_device(device)
@@ -399,6 +427,31 @@ class Trajectories:
 
     def set_pm_path(self, path):
         mfq_set_pm_path(self.ctx, path)
+
+    def autotune(self, protocol, gamma, dt, seed, probe_steps=4, cache=None):
+        """Tune the execution form (mfq_autotune) or reuse a choice cached in the JSON file
+        `cache` under a key of device, lattice, N, batch, protocol and precision."""
+        import json
+        import os
+        import torch
+        key = "|".join(str(x) for x in (torch.cuda.get_device_name(self.device), self.lat.dim,
+                                         self.lat.Lx, self.lat.Ly, self.N, self.n_traj, protocol,
+                                         self.precision))
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+        if key in table:
+            mfq_set_tuning(self.ctx, table[key]["path"], table[key]["tile"])
+            return dict(table[key], cached=True)
+        g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (self.n_traj,))
+        res = mfq_autotune(self.ctx, protocol, g, dt, seed, probe_steps)
+        if cache:
+            table[key] = res
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return dict(res, cached=False)
 
     def use_graphs(self, enable=True):
         mfq_use_graphs(self.ctx, enable)

@@ -145,6 +145,33 @@ int main() {
     CHECK(p.job(a)->S.size() == 5);  // steps 7, 14, 21, 28 and the last (30)
     CHECK(p.job(b)->S.size() == 3);  // steps 10, 20, 30
   }
+  {  // scheduling: shortest work to the next completion first, within the width budget
+    Policy p(1 << 30, 1, fake_bytes);
+    const uint64_t big = p.submit(job(512, 100)), mid = p.submit(job(128, 100));
+    const uint64_t small = p.submit(job(64, 100)), tiny_late = p.submit(job(64, 10));
+    for (auto &x : p.plan()) if (x.kind == Action::CREATE) p.group_created(x.group);
+    const int gb = p.job(big)->group, gm = p.job(mid)->group, gs = p.job(small)->group;
+    const int gt = p.job(tiny_late)->group;
+    CHECK(p.next_completion_work(gt) < p.next_completion_work(gs));
+    CHECK(p.next_completion_work(gs) < p.next_completion_work(gm));
+    CHECK(p.next_completion_work(gm) < p.next_completion_work(gb));
+    // a budget of one element: only the group nearest to a completion runs
+    std::vector<int> one = p.schedule(1.0);
+    CHECK(one.size() == 1 && one[0] == gt);
+    // a budget that the two smallest groups (64 * 32 elements each) do not fill
+    std::vector<int> some = p.schedule(64.0 * 32 * 2 + 1);
+    CHECK(some.size() == 3 && some[0] == gt && some[1] == gs && some[2] == gm);
+    // an unlimited budget runs everything, still in that order
+    std::vector<int> all = p.schedule(1e30);
+    CHECK(all.size() == 4 && all[3] == gb);
+    // progress changes the order: with one step left the big job (about 1.1e9 flop) comes
+    // before the untouched L=128 job (100 steps of 1.7e7), behind the L=64 one (2.1e8)
+    p.advanced(gb, 99, 0.1);
+    p.advanced(gt, 10, 0.1);
+    p.complete(tiny_late, 1.0);
+    std::vector<int> after = p.schedule(1e30);
+    CHECK(after.size() == 3 && after[0] == gs && after[1] == gb && after[2] == gm);
+  }
   std::printf(failures ? "policy checks: %d failures\n" : "policy checks: all passed\n", failures);
   return failures ? 1 : 0;
 }
