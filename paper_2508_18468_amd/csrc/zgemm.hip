@@ -73,7 +73,11 @@ __device__ inline void upper_tile(int t, int &tm, int &tn) {
 
 // GATHER: storage rows of A / B are looked up through idxA / idxB.
 // EDGE: bounds-checked loads and stores (M, N or K not multiples of the tile).
-template <int OPA, int OPB, int MT, int NT, int KT, bool GATHER, bool EDGE>
+// FL: compile-time features, so that the plain contractions carry none of their code.
+enum { FL_MASK = 1,      // triangular operands (aUpper / bUpper) masked at load
+       FL_NEAR_ID = 2 }; // near-identity epilogue (R1, maxdev)
+
+template <int OPA, int OPB, int MT, int NT, int KT, bool GATHER, bool EDGE, int FL = 0>
 __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   // waves: 2 along M; NT/32 along N (2 for 64x64 tiles, 4 for 128x128 tiles)
   constexpr int WM = 2, WN = NT / 32, NTHR = 64 * WM * WN;
@@ -133,7 +137,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPA == OP_N ? a_slow + DA * i : a_fast;
       const int gm = m0 + m, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if ((!EDGE || (gm < g.M && gk < kend)) && !(g.aUpper && gk < gm)) {
+      if ((!EDGE || (gm < g.M && gk < kend)) && !((FL & FL_MASK) && g.aUpper && gk < gm)) {
         cplx v;
         if (OPA == OP_N) {
           const long row = idxA ? idxA[gm] : gm;
@@ -153,7 +157,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPB == OP_N ? b_fast : b_slow + DB * i;
       const int gn = n0 + n, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if ((!EDGE || (gn < g.N && gk < kend)) && !(g.bUpper && gk > gn)) {
+      if ((!EDGE || (gn < g.N && gk < kend)) && !((FL & FL_MASK) && g.bUpper && gk > gn)) {
         cplx v;
         if (OPB == OP_N) {
           const long row = idxB ? idxB[gk] : gk;
@@ -244,7 +248,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   const bool useC = (g.beta.re != 0.0 || g.beta.im != 0.0);
   const cplx *Cin = g.Cin ? g.Cin + (long)b * g.sCin : nullptr;
   cplx *D = g.D + (long)b * g.sD;
-  cplx *R1 = g.R1 ? g.R1 + (long)b * g.sD : nullptr;
+  cplx *R1 = (FL & FL_NEAR_ID) ? g.R1 + (long)b * g.sD : nullptr;
   double dmax = 0.0;
   const double qnan = __longlong_as_double(0x7ff8000000000000ll);
 #pragma unroll
@@ -266,14 +270,14 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
           yi += g.beta.re * c.im + g.beta.im * c.re;
         }
         D[row + (long)col * g.ldd] = cplx{yr, yi};
-        if (R1) {
+        if (FL & FL_NEAR_ID) {
           const double er = row == col ? yr - 1.0 : yr;
           const double a = fabs(er) + fabs(yi);
           dmax = (!(a <= 1e300) || dmax != dmax) ? qnan : fmax(dmax, a);
           R1[row + (long)col * g.ldd] = row == col ? cplx{1.0 - 0.5 * er, 0.0} : cplx{-yr, -yi};
         }
       }
-  if (R1) {  // non-negative doubles order like their bit patterns; NaN is above them all
+  if (FL & FL_NEAR_ID) {  // non-negative doubles order like their bit patterns; NaN is above them all
     for (int o = 32; o > 0; o >>= 1) {
       const double y = __shfl_xor(dmax, o, 64);
       dmax = (y != y || dmax != dmax) ? qnan : fmax(dmax, y);
@@ -289,9 +293,9 @@ constexpr int kchunk() { return 16; }
 template <int NT>
 constexpr int nthreads() { return 64 * 2 * (NT / 32); }
 
-template <int OPA, int OPB, int MT, int NT, bool GATHER, bool EDGE>
+template <int OPA, int OPB, int MT, int NT, bool GATHER, bool EDGE, int FL = 0>
 __global__ __launch_bounds__(nthreads<NT>()) void zgemm_kernel(GemmDesc g) {
-  zgemm_body<OPA, OPB, MT, NT, kchunk<MT>(), GATHER, EDGE>(g);
+  zgemm_body<OPA, OPB, MT, NT, kchunk<MT>(), GATHER, EDGE, FL>(g);
 }
 
 // The propagator product U <- P U gets its own symbols so that profilers can
@@ -322,25 +326,39 @@ bool needs_edge(const GemmDesc &g) {
   return (g.M % MT) || (g.N % NT) || (g.K % KT);
 }
 
-template <int MT, int NT, bool GATHER, bool EDGE>
+template <int MT, int NT, bool GATHER, bool EDGE, int FL = 0>
 void launch_ops(const GemmDesc &g, dim3 grid, hipStream_t s) {
   const dim3 block(nthreads<NT>());
   if (g.opA == OP_N && g.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
   else if (g.opA == OP_C && g.opB == OP_N)
-    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
   else if (g.opA == OP_N && g.opB == OP_C)
-    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
   else
-    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_C, MT, NT, GATHER, EDGE>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_C, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
 }
 
 template <int MT, int NT>
 hipError_t launch(const GemmDesc &g, hipStream_t s) {
   const dim3 grid(grid_size<MT, NT>(g));
-  if (g.idxA || g.idxB) launch_ops<MT, NT, true, true>(g, grid, s);
-  else if (needs_edge<MT, NT>(g)) launch_ops<MT, NT, false, true>(g, grid, s);
-  else launch_ops<MT, NT, false, false>(g, grid, s);
+  const bool edge = needs_edge<MT, NT>(g);
+  if (g.R1) {  // near-identity epilogue: the upper Gram U^+ U of a Cholesky-QR pass
+    if (g.opA != OP_C || g.opB != OP_N || g.idxA || g.idxB || g.aUpper || g.bUpper) return hipErrorInvalidValue;
+    if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, false, true, FL_NEAR_ID>), grid,
+                                 dim3(nthreads<NT>()), 0, s, g);
+    else hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, false, false, FL_NEAR_ID>), grid,
+                            dim3(nthreads<NT>()), 0, s, g);
+  } else if (g.idxA || g.idxB) {
+    launch_ops<MT, NT, true, true>(g, grid, s);
+  } else if (g.aUpper || g.bUpper) {
+    if (edge) launch_ops<MT, NT, false, true, FL_MASK>(g, grid, s);
+    else launch_ops<MT, NT, false, false, FL_MASK>(g, grid, s);
+  } else if (edge) {
+    launch_ops<MT, NT, false, true>(g, grid, s);
+  } else {
+    launch_ops<MT, NT, false, false>(g, grid, s);
+  }
   return hipGetLastError();
 }
 
