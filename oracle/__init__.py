@@ -17,6 +17,7 @@ dynamics of monitored noninteracting fermions on graphics processing units":
 * QR re-orthonormalisation              -- Appendix A (after each step)
 * entanglement entropy                  -- Sec. II, entropy formula
 * mutual information                    -- Sec. IV
+* density correlation C(r), G_AB        -- Sec. II Eq. (2), Sec. IV Eq. (5)
 
 Random numbers: Philox4x64-10 (Salmon et al., SC'11), implemented here from
 its published definition, independently of the GPU's implementation.
@@ -32,7 +33,8 @@ from .trajectory import (initial_state, propagate, born_probabilities,
                          pm_measure, qsd_update, reorthonormalize, step,
                          run_trajectory)
 from .observables import (correlation_matrix, region_spectrum, entropy_from_spectrum,
-                          entanglement_entropy, mutual_information)
+                          entanglement_entropy, mutual_information, density_correlation,
+                          particle_covariance)
 
 __all__ = [
     "Lattice", "hopping_matrix", "default_occupied", "propagator",
@@ -40,5 +42,5 @@ __all__ = [
     "initial_state", "propagate", "born_probabilities", "pm_measure", "qsd_update",
     "reorthonormalize", "step", "run_trajectory",
     "correlation_matrix", "region_spectrum", "entropy_from_spectrum",
-    "entanglement_entropy", "mutual_information",
+    "entanglement_entropy", "mutual_information", "density_correlation", "particle_covariance",
 ]
