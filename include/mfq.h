@@ -139,6 +139,26 @@ mfq_status mfq_region_spectrum(mfq_ctx *ctx, const int32_t *region, int32_t n_si
 mfq_status mfq_mutual_info(mfq_ctx *ctx, const int32_t *A, int32_t nA, const int32_t *B,
                            int32_t nB, double *I_host);
 
+/* Density-density correlation of Sec. II, Eq. (2), on a 1d ring: by Wick's theorem
+ * C_ij = -D_ij D_ji = -|C_ij|^2 for i != j, and C(r) is its average over the ordered site
+ * pairs at ring distance r = min(|i - j|, L - |i - j|).  Cr_host[t * (L/2) + r - 1] for
+ * r = 1 .. L/2, one trajectory each (the average over trajectories is the caller's).
+ * Computed from the upper triangle of C = U U^+ on the matrix cores with the sums of
+ * |C_ij|^2 along each diagonal formed in the product's epilogue (C is never stored).
+ * Allocates a buffer on first use.  Synchronises.
+ * Errors: MFQ_EINVAL (not a 1d lattice, NULL output), MFQ_ESTATE, MFQ_ENOMEM, MFQ_EDEVICE. */
+mfq_status mfq_density_correlation(mfq_ctx *ctx, double *Cr_host);
+
+/* Particle-number covariance of Sec. IV, Eq. (5): G_AB = -sum_{i in A, j in B} C_ij
+ * = sum_{i in A, j in B} |C_ij|^2 for disjoint site lists A and B (ascending), i.e. minus
+ * the covariance of the particle numbers of A and B; G_host[t] per trajectory.  Computed
+ * from C_AB = U_A U_B^+ on the matrix cores with |C_ij|^2 summed in the product's epilogue.
+ * Allocates a buffer on first use.  Synchronises.
+ * Errors: MFQ_EINVAL (overlapping or invalid regions, NULL output), MFQ_ESTATE, MFQ_ENOMEM,
+ * MFQ_EDEVICE. */
+mfq_status mfq_particle_covariance(mfq_ctx *ctx, const int32_t *A, int32_t nA, const int32_t *B,
+                                   int32_t nB, double *G_host);
+
 /* Born probabilities <n_i> = sum_k |U_ik|^2 of the current state (Appendix A):
  * p_host[t * L + i], caller-owned.  Synchronises. */
 mfq_status mfq_occupations(mfq_ctx *ctx, double *p_host);

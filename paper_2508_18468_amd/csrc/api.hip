@@ -64,6 +64,9 @@ struct mfq_ctx {
   // mfq_run: execution path and its observation buffer; GEMM tile choice
   int run_path = 0;   // MFQ_PATH_AUTO
   int tile_mode = 0;  // MFQ_TILE_AUTO
+  // correlation observables: tile partials and results (allocated on first use)
+  double *red_buf = nullptr;
+  size_t red_cap = 0;
   int g_tile = -1;    // tile choice the cached graph was captured with
   double *run_S = nullptr;
   size_t run_S_cap = 0;
@@ -468,6 +471,7 @@ mfq_status mfq_destroy(mfq_ctx *c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   drop_graph(c);
   if (c->run_S) (void)hipFree(c->run_S);
+  if (c->red_buf) (void)hipFree(c->red_buf);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -646,6 +650,7 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   const size_t need = (size_t)std::max(n_obs, 1) * c->B;
   if (need > c->run_S_cap) {
     if (c->run_S) (void)hipFree(c->run_S);
+  if (c->red_buf) (void)hipFree(c->red_buf);
     c->run_S = nullptr;
     c->run_S_cap = 0;
     HIPCHK(hipMalloc(&c->run_S, need * sizeof(double)), "observation buffer");
@@ -672,6 +677,90 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
                           c->stream), "observation download");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   c->step += n_steps;
+  return check_flag(c);
+}
+
+namespace {
+
+mfq_status ensure_red(mfq_ctx *c, size_t n) {
+  if (n <= c->red_cap) return MFQ_OK;
+  if (c->red_buf) (void)hipFree(c->red_buf);
+  c->red_buf = nullptr;
+  c->red_cap = 0;
+  if (hipMalloc(&c->red_buf, n * sizeof(double)) != hipSuccess)
+    return fail(c, MFQ_ENOMEM, "correlation buffer");
+  c->red_cap = n;
+  return MFQ_OK;
+}
+
+}  // namespace
+
+mfq_status mfq_density_correlation(mfq_ctx *c, double *Cr_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!Cr_host) return fail(c, MFQ_EINVAL, "Cr_host is NULL");
+  if (c->lat.dim != 1) return fail(c, MFQ_EINVAL, "C(r) is defined for 1d rings");
+  TileScope tiles(c);
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int L = c->L, half = L / 2;
+  GemmDesc g{};
+  g.alpha = cplx{1.0, 0.0};
+  g.M = L; g.N = L; g.K = c->N; g.batch = c->B;
+  g.A = c->X[c->cur]; g.lda = L; g.sA = (long)L * c->N; g.opA = OP_N;
+  g.B = c->X[c->cur]; g.ldb = L; g.sB = (long)L * c->N; g.opB = OP_C;
+  g.tri = TRI_UPPER;
+  const size_t np = zgemm_partials(g), nout = (size_t)half * c->B;
+  mfq_status st = ensure_red(c, np + nout);
+  if (st) return st;
+  g.part = c->red_buf;
+  {
+    PhaseTimer t(c, MFQ_PHASE_OBSERVE);
+    HIPCHK(zgemm_ring_bins(g, L, c->red_buf + np, c->stream), "density correlation");
+  }
+  HIPCHK(hipMemcpyAsync(Cr_host, c->red_buf + np, nout * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "C(r) download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return check_flag(c);
+}
+
+mfq_status mfq_particle_covariance(mfq_ctx *c, const int32_t *A, int32_t nA, const int32_t *B, int32_t nB,
+                                   double *G_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!G_host) return fail(c, MFQ_EINVAL, "G_host is NULL");
+  mfq_status st = validate_region(c, A, nA);
+  if (st) return st;
+  if ((st = validate_region(c, B, nB))) return st;
+  for (int i = 0, j = 0; i < nA && j < nB;) {  // both ascending: disjoint iff no common entry
+    if (A[i] == B[j]) return fail(c, MFQ_EINVAL, "regions A and B must be disjoint");
+    if (A[i] < B[j]) ++i;
+    else ++j;
+  }
+  if (nA == 0 || nB == 0) {
+    for (int b = 0; b < c->B; ++b) G_host[b] = 0.0;
+    return MFQ_OK;
+  }
+  TileScope tiles(c);
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(c->region, A, nA * sizeof(int), hipMemcpyHostToDevice, c->stream), "region upload");
+  HIPCHK(hipMemcpyAsync(c->region + nA, B, nB * sizeof(int), hipMemcpyHostToDevice, c->stream),
+         "region upload");
+  const int L = c->L;
+  GemmDesc g{};
+  g.alpha = cplx{1.0, 0.0};
+  g.M = nA; g.N = nB; g.K = c->N; g.batch = c->B;
+  g.A = c->X[c->cur]; g.lda = L; g.sA = (long)L * c->N; g.opA = OP_N; g.idxA = c->region;
+  g.B = c->X[c->cur]; g.ldb = L; g.sB = (long)L * c->N; g.opB = OP_C; g.idxB = c->region + nA;
+  const size_t np = zgemm_partials(g);
+  if ((st = ensure_red(c, np + c->B))) return st;
+  g.part = c->red_buf;
+  {
+    PhaseTimer t(c, MFQ_PHASE_OBSERVE);
+    HIPCHK(zgemm_tile_sum(g, c->red_buf + np, c->stream), "particle covariance");
+  }
+  HIPCHK(hipMemcpyAsync(G_host, c->red_buf + np, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "G_AB download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   return check_flag(c);
 }
 

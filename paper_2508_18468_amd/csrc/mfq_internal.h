@@ -37,6 +37,10 @@ struct GemmDesc {
   // raises it to NaN).  *maxdev must be zeroed beforehand.
   cplx *R1;
   double *maxdev;
+  // Reduction epilogues (D is then not written): with part set, a TRI_UPPER square product
+  // stores per tile the sums of |D_ij|^2 (i < j) along each diagonal j - i, a general one
+  // stores per tile the sum of |D_ij|^2 (see zgemm_partials, zgemm_ring_bins, zgemm_tile_sum).
+  double *part;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
@@ -47,6 +51,14 @@ hipError_t zgemm(const GemmDesc &g, hipStream_t s);
 enum { GEMM_TILE_AUTO = 0, GEMM_TILE_SMALL = 1, GEMM_TILE_LARGE = 2 };
 void set_gemm_tile_mode(int mode);
 int gemm_tile_mode();
+// Doubles of partial results that a reduction-epilogue product g writes (0 if none).
+size_t zgemm_partials(const GemmDesc &g);
+// From the diagonal partials of the upper product C = U U^+ (M = N = L): for every batch entry
+// and ring distance r = 1 .. L/2, out[b * (L/2) + r - 1] = C(r) = -(sum over ordered pairs
+// i != j at ring distance r of |C_ij|^2) / (their number).  Launches the product as well.
+hipError_t zgemm_ring_bins(const GemmDesc &g, int L, double *out, hipStream_t s);
+// Launches the product and sums its tile partials per batch entry: out[b] = sum |D_ij|^2.
+hipError_t zgemm_tile_sum(const GemmDesc &g, double *out, hipStream_t s);
 // Same contraction (op N, op N), launched under a distinct kernel name.
 hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s);
 

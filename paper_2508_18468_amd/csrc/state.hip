@@ -86,6 +86,50 @@ __global__ __launch_bounds__(256) void born_kernel(cplx *U, double *p, int L, in
   }
 }
 
+// Same operation with the rows held in registers between the reduction and
+// the scaling, so U is read once and written once: a workgroup owns 16
+// consecutive rows of one trajectory; thread t holds row t % 16 at columns
+// t / 16 + 16 v (v < VPT, N <= 16 VPT).  The 16 partial sums of a row are
+// combined in a fixed order (wave shuffles, then the four waves in LDS).
+template <bool HOMODYNE, int VPT>
+__global__ __launch_bounds__(256) void born_rows_kernel(cplx *U, double *p, int L, int N,
+                                                        const double *gamma, double dt, uint64_t seed,
+                                                        const uint64_t *uid, const int64_t *step_ptr,
+                                                        int step_offset, const int64_t *step_base) {
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int r = tid & 15, c0 = tid >> 4;
+  const int i = blockIdx.x * 16 + r;
+  const bool row_ok = i < L;
+  cplx *Ub = U + (long)b * L * N;
+  cplx a[VPT];
+  double s = 0.0;
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    const int k = c0 + 16 * v;
+    a[v] = (row_ok && k < N) ? Ub[i + (long)k * L] : cplx{0.0, 0.0};
+    s += a[v].re * a[v].re + a[v].im * a[v].im;
+  }
+  // lanes r, r+16, r+32, r+48 of a wave hold the same row
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  __shared__ double part[4][16];
+  if ((tid & 63) < 16) part[tid >> 6][r] = s;
+  __syncthreads();
+  const double pi = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+  if (c0 == 0 && row_ok) p[(long)b * L + i] = pi;
+  if (!HOMODYNE || !row_ok) return;
+  const double g = gamma[b];
+  const uint64_t step = (uint64_t)(*step_ptr + step_offset - step_base[b]);
+  const u64x4 w = philox4x64_10(seed, uid[b], step, (uint64_t)i, PURPOSE_HOMODYNE, 0);
+  const double z = sqrt(-2.0 * log(u01(w.v[0]))) * cos(6.283185307179586 * u01(w.v[1]));
+  const double f = exp(sqrt(g * dt) * z + g * (2.0 * pi - 1.0) * dt);
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) {
+    const int k = c0 + 16 * v;
+    if (k < N) Ub[i + (long)k * L] = cplx{a[v].re * f, a[v].im * f};
+  }
+}
+
 // Projective measurement of one step, one trajectory per workgroup (see
 // pm_measure_block).
 __global__ __launch_bounds__(256) void pm_kernel(cplx *U, int L, int N, const double *gamma,
@@ -165,6 +209,19 @@ hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t 
 hipError_t born_homodyne(cplx *U, double *p, int L, int N, int B, const double *gamma, double dt,
                          uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
                          const int64_t *step_base, hipStream_t s) {
+  if (N <= 16 * 32) {  // rows in registers: one read and one write of U
+    const dim3 g16((L + 15) / 16, B);
+    if (N <= 16 * 8)
+      hipLaunchKernelGGL((born_rows_kernel<true, 8>), g16, dim3(256), 0, s, U, p, L, N, gamma, dt, seed,
+                         uid, step_ptr, step_offset, step_base);
+    else if (N <= 16 * 16)
+      hipLaunchKernelGGL((born_rows_kernel<true, 16>), g16, dim3(256), 0, s, U, p, L, N, gamma, dt, seed,
+                         uid, step_ptr, step_offset, step_base);
+    else
+      hipLaunchKernelGGL((born_rows_kernel<true, 32>), g16, dim3(256), 0, s, U, p, L, N, gamma, dt, seed,
+                         uid, step_ptr, step_offset, step_base);
+    return hipGetLastError();
+  }
   dim3 grid((L + 255) / 256, B);
   hipLaunchKernelGGL(born_kernel<true>, grid, dim3(256), 0, s, U, p, L, N, gamma, dt, seed, uid,
                      step_ptr, step_offset, step_base);

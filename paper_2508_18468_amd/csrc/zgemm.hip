@@ -71,11 +71,94 @@ __device__ inline void upper_tile(int t, int &tm, int &tn) {
   tm = t - c * (c + 1) / 2;
 }
 
-// GATHER: storage rows of A / B are looked up through idxA / idxB.
-// EDGE: bounds-checked loads and stores (M, N or K not multiples of the tile).
 // FL: compile-time features, so that the plain contractions carry none of their code.
 enum { FL_MASK = 1,      // triangular operands (aUpper / bUpper) masked at load
-       FL_NEAR_ID = 2 }; // near-identity epilogue (R1, maxdev)
+       FL_NEAR_ID = 2,   // near-identity epilogue (R1, maxdev)
+       FL_SQSUM = 4,     // per-tile sum of |D_ij|^2 into part (D not written)
+       FL_DIAG = 8 };    // per-tile sums of |D_ij|^2, i < j, along each diagonal (D not written)
+
+// Reduction epilogues.  scratch: the A-plane LDS of the tile (2 KT (MT + 1) doubles), free
+// once the K loop is over.  Every sum runs in a fixed order, so results are reproducible.
+template <int MT, int NT, int KT, bool EDGE, int FL, int IM, int JN>
+__device__ __forceinline__ void reduce_epilogue(const GemmDesc &g, const d4 (&acc_re)[IM][JN],
+                                                const d4 (&acc_im)[IM][JN], double *scratch, int b,
+                                                int t, int tm, int tn, int m0, int n0, int n_upper,
+                                                int n_tiles) {
+  constexpr int WM = 2, WN = NT / 32, NTHR = 64 * WM * WN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave % WM, wc = wave / WM;
+  auto value = [&](int i, int j, int r, int &lr, int &lc) {
+    lr = wr * (MT / WM) + i * 16 + (lane >> 4) + 4 * r;
+    lc = wc * (NT / WN) + j * 16 + (lane & 15);
+    const int row = m0 + lr, col = n0 + lc;
+    bool ok = !EDGE || (row < g.M && col < g.N);
+    if ((FL & FL_DIAG) != 0) ok = ok && row < col;
+    if (!ok) return 0.0;
+    const double xr = acc_re[i][j][r], xi = acc_im[i][j][r];
+    const double yr = g.alpha.re * xr - g.alpha.im * xi, yi = g.alpha.re * xi + g.alpha.im * xr;
+    return yr * yr + yi * yi;
+  };
+  if constexpr ((FL & FL_SQSUM) != 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+      for (int j = 0; j < JN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int lr, lc;
+          s += value(i, j, r, lr, lc);
+        }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    __syncthreads();
+    if (lane == 0) scratch[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < NTHR / 64; ++w) tot += scratch[w];
+      g.part[(long)b * n_tiles + tm + (long)tn * ((g.M + MT - 1) / MT)] = tot;
+    }
+  } else {
+    // diagonal d = lc - lr in [-(MT-1), NT-1], offset o = d + MT - 1; the tile passes
+    // through the scratch CR rows at a time
+    constexpr int ND = MT + NT - 1, CR = 2 * KT * (MT + 1) / NT, NQ = (ND + NTHR - 1) / NTHR;
+    double accd[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) accd[q] = 0.0;
+    for (int r0 = 0; r0 < MT; r0 += CR) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < IM; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            int lr, lc;
+            const double v = value(i, j, r, lr, lc);
+            if (lr >= r0 && lr < r0 + CR) scratch[(lr - r0) * NT + lc] = v;
+          }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int o = tid + NTHR * q;
+        if (o >= ND) continue;
+        const int d = o - (MT - 1);
+        for (int lr = r0; lr < r0 + CR; ++lr) {
+          const int lc = lr + d;
+          if (lc >= 0 && lc < NT) accd[q] += scratch[(lr - r0) * NT + lc];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int o = tid + NTHR * q;
+      if (o < ND) g.part[((long)b * n_upper + t) * ND + o] = accd[q];
+    }
+  }
+}
+
+// GATHER: storage rows of A / B are looked up through idxA / idxB.
+// EDGE: bounds-checked loads and stores (M, N or K not multiples of the tile).
 
 template <int OPA, int OPB, int MT, int NT, int KT, bool GATHER, bool EDGE, int FL = 0>
 __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
@@ -244,6 +327,11 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
     __syncthreads();
   }
 
+  if constexpr ((FL & (FL_SQSUM | FL_DIAG)) != 0) {
+    reduce_epilogue<MT, NT, KT, EDGE, FL>(g, acc_re, acc_im, &Ar[0][0][0], b, t, tm, tn, m0, n0,
+                                          map.per_group, map.tilesM * map.tilesN);
+    return;
+  }
   // epilogue: D = alpha * acc + beta * Cin
   const bool useC = (g.beta.re != 0.0 || g.beta.im != 0.0);
   const cplx *Cin = g.Cin ? g.Cin + (long)b * g.sCin : nullptr;
@@ -342,7 +430,23 @@ void launch_ops(const GemmDesc &g, dim3 grid, hipStream_t s) {
 template <int MT, int NT>
 hipError_t launch(const GemmDesc &g, hipStream_t s) {
   const dim3 grid(grid_size<MT, NT>(g));
+  const dim3 block(nthreads<NT>());
   const bool edge = needs_edge<MT, NT>(g);
+  if (g.part) {  // reduction epilogues: products U_X U_Y^+ only
+    if (g.opA != OP_N || g.opB != OP_C || g.R1 || g.aUpper || g.bUpper) return hipErrorInvalidValue;
+    if (g.tri == TRI_UPPER) {
+      if (g.M != g.N || g.idxA || g.idxB) return hipErrorInvalidValue;
+      if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, false, true, FL_DIAG>), grid, block, 0, s, g);
+      else hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, false, false, FL_DIAG>), grid, block, 0, s, g);
+    } else if (g.idxA || g.idxB) {
+      hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, true, true, FL_SQSUM>), grid, block, 0, s, g);
+    } else if (edge) {
+      hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, false, true, FL_SQSUM>), grid, block, 0, s, g);
+    } else {
+      hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, false, false, FL_SQSUM>), grid, block, 0, s, g);
+    }
+    return hipGetLastError();
+  }
   if (g.R1) {  // near-identity epilogue: the upper Gram U^+ U of a Cholesky-QR pass
     if (g.opA != OP_C || g.opB != OP_N || g.idxA || g.idxB || g.aUpper || g.bUpper) return hipErrorInvalidValue;
     if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, false, true, FL_NEAR_ID>), grid,
@@ -381,16 +485,83 @@ hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t zgemm(const GemmDesc &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
-  if (tl_tile_mode == GEMM_TILE_SMALL) return launch<64, 64>(g, s);
-  // Large tiles only when every dimension fills them (and, by default, when there is
-  // enough work to occupy the chip with them).
+// Tile edge the dispatcher uses for g: large tiles only when every dimension fills them
+// (and, by default, when there is enough work to occupy the chip with them).
+int pick_tile(const GemmDesc &g) {
+  if (tl_tile_mode == GEMM_TILE_SMALL) return 64;
   const long work = (long)g.M * g.N * g.batch;
   if (g.M >= 128 && g.N >= 128 && g.K >= 128 &&
       (tl_tile_mode == GEMM_TILE_LARGE || work >= (1L << 22)))
-    return launch<128, 128>(g, s);
-  return launch<64, 64>(g, s);
+    return 128;
+  return 64;
+}
+
+hipError_t zgemm(const GemmDesc &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  return pick_tile(g) == 128 ? launch<128, 128>(g, s) : launch<64, 64>(g, s);
+}
+
+size_t zgemm_partials(const GemmDesc &g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return 0;
+  const long T = pick_tile(g), tm = (g.M + T - 1) / T, tn = (g.N + T - 1) / T;
+  if (g.tri == TRI_UPPER) return (size_t)g.batch * (tm * (tm + 1) / 2) * (2 * T - 1);
+  return (size_t)g.batch * tm * tn;
+}
+
+namespace {
+
+// C(r) from the diagonal partials (see zgemm_ring_bins): thread per distance r; the upper
+// pair (i, j), j - i = e, lies at ring distance min(e, L - e).
+__global__ __launch_bounds__(256) void ring_bins_kernel(const double *part, int L, int T, int n_upper,
+                                                        double *out) {
+  const int b = blockIdx.y, r = 1 + blockIdx.x * 256 + threadIdx.x;
+  if (r > L / 2) return;
+  const int ND = 2 * T - 1;
+  const double *pb = part + (long)b * n_upper * ND;
+  const int e1 = r, e2 = L - r;
+  double s = 0.0;
+  for (int t = 0; t < n_upper; ++t) {
+    int tm, tn;
+    upper_tile(t, tm, tn);
+    const int delta = (tn - tm) * T;
+    int o = e1 - delta + (T - 1);
+    if (o >= 0 && o < ND) s += pb[(long)t * ND + o];
+    if (e2 != e1) {
+      o = e2 - delta + (T - 1);
+      if (o >= 0 && o < ND) s += pb[(long)t * ND + o];
+    }
+  }
+  // ordered pairs at distance r: 2L (r < L/2) or L (r = L/2); s counts each once
+  out[(long)b * (L / 2) + r - 1] = 2 * r == L ? -2.0 * s / L : -s / L;
+}
+
+__global__ __launch_bounds__(64) void tile_sum_kernel(const double *part, long n_tiles, double *out) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (long t = 0; t < n_tiles; ++t) s += part[(long)b * n_tiles + t];
+  out[b] = s;
+}
+
+}  // namespace
+
+hipError_t zgemm_ring_bins(const GemmDesc &g, int L, double *out, hipStream_t s) {
+  if (!g.part || g.tri != TRI_UPPER || g.M != L || g.N != L) return hipErrorInvalidValue;
+  hipError_t e = zgemm(g, s);
+  if (e != hipSuccess) return e;
+  const int T = pick_tile(g), tiles = (L + T - 1) / T;
+  hipLaunchKernelGGL(ring_bins_kernel, dim3((L / 2 + 255) / 256, g.batch), dim3(256), 0, s, g.part, L, T,
+                     tiles * (tiles + 1) / 2, out);
+  return hipGetLastError();
+}
+
+hipError_t zgemm_tile_sum(const GemmDesc &g, double *out, hipStream_t s) {
+  if (!g.part || g.tri == TRI_UPPER) return hipErrorInvalidValue;
+  hipError_t e = zgemm(g, s);
+  if (e != hipSuccess) return e;
+  const long T = pick_tile(g), n_tiles = ((g.M + T - 1) / T) * ((g.N + T - 1) / T);
+  hipLaunchKernelGGL(tile_sum_kernel, dim3(g.batch), dim3(64), 0, s, g.part, n_tiles, out);
+  return hipGetLastError();
 }
 
 }  // namespace mfq

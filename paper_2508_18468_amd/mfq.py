@@ -88,6 +88,9 @@ _SIGS = {
     "mfq_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_particle_covariance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_reset_trajectory": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
     "mfq_engine_create": (ctypes.c_int32, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_void_p)]),
@@ -192,6 +195,20 @@ def mfq_mutual_info(ctx, A, B, n_traj):
     I = np.zeros(n_traj)
     _check(ctx, lib().mfq_mutual_info(ctx, _ptr(a), a.size, _ptr(b), b.size, _ptr(I)))
     return I
+
+
+def mfq_density_correlation(ctx, n_traj, L):
+    """C(r) of Eq. (2), r = 1 .. L/2, per trajectory: an (n_traj, L//2) array."""
+    Cr = np.zeros((n_traj, L // 2))
+    _check(ctx, lib().mfq_density_correlation(ctx, _ptr(Cr)))
+    return Cr
+
+
+def mfq_particle_covariance(ctx, A, B, n_traj):
+    a, b = _i32(A), _i32(B)
+    G = np.zeros(n_traj)
+    _check(ctx, lib().mfq_particle_covariance(ctx, _ptr(a), a.size, _ptr(b), b.size, _ptr(G)))
+    return G
 
 
 def mfq_occupations(ctx, n_traj, L):
@@ -395,6 +412,12 @@ class Trajectories:
 
     def occupations(self):
         return mfq_occupations(self.ctx, self.n_traj, self.L)
+
+    def density_correlation(self):
+        return mfq_density_correlation(self.ctx, self.n_traj, self.L)
+
+    def particle_covariance(self, A, B):
+        return mfq_particle_covariance(self.ctx, A, B, self.n_traj)
 
     def pm_events(self, max_events=None):
         return mfq_pm_events(self.ctx, self.n_traj, self.L if max_events is None else max_events)
