@@ -8,7 +8,8 @@
 // inverse R^{-1} assembled block column by block column from GEMMs, and the
 // triangular product U R^{-1} (zero blocks of R^{-1} skipped).  Two passes
 // (Cholesky-QR2) bring U^+ U to identity at working precision for the
-// condition numbers a step produces.
+// condition numbers a step produces; the second pass keeps U as it is when its
+// Gram certifies |U^+ U - I| <= CHOL_KEEP_MAX entrywise.
 #include "mfq_internal.h"
 
 namespace mfq {
@@ -199,13 +200,18 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
       if ((e = zgemm(g, s)) != hipSuccess) return e;
     }
   }
-  // Uout = Uin R^{-1}
+  // Uout = Uin R^{-1}; in the second pass a copy when Uin is already orthonormal to
+  // CHOL_KEEP_MAX (decided on the device from the Gram's max |G - I|)
   {
     GemmDesc g = desc();
     g.M = L; g.N = N; g.K = N; g.batch = B;
     g.A = Uin; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
     g.B = wk.Rinv; g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;
     g.D = Uout; g.ldd = L; g.sD = (long)L * N;
+    if (near_identity) {
+      g.copy_if_le = wk.dev;
+      g.copy_thr = CHOL_KEEP_MAX;
+    }
     if ((e = zgemm(g, s)) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -41,6 +41,10 @@ struct GemmDesc {
   // stores per tile the sums of |D_ij|^2 (i < j) along each diagonal j - i, a general one
   // stores per tile the sum of |D_ij|^2 (see zgemm_partials, zgemm_ring_bins, zgemm_tile_sum).
   double *part;
+  // Certified skip of a triangular product U R^{-1} with R^{-1} = I + O(E) (op N x op N,
+  // square B, bUpper): if *copy_if_le <= copy_thr, D = A is copied instead.
+  const double *copy_if_le;
+  double copy_thr;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
@@ -120,6 +124,10 @@ struct CholWork {
 constexpr int CHOL_NB = 64;
 // Largest |U^+ U - I| entry for which the second pass uses the first-order factor.
 constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
+// Largest |U^+ U - I| entry for which the second pass keeps U as it is: the first pass
+// already delivered an orthonormal basis to that accuracy, which the second pass's own
+// rounding (about L eps per entry of the Gram) would not improve on.
+constexpr double CHOL_KEEP_MAX = 1e-13;
 // One Cholesky-QR pass: Uout = Uin * R^{-1}, R = chol(Uin^+ Uin).  With
 // near_identity, the Gram is first tested against I: if every entry of
 // E = G - I is below CHOL_FIRST_ORDER_MAX, R^{-1} = I - triu(E) + diag(E)/2 (the

@@ -242,3 +242,20 @@ def test_strong_homodyne_uses_full_second_pass():
         assert np.abs(np.conj(U[t].T) @ U[t] - np.eye(32)).max() < 1e-12
         assert np.abs(corr(U[t]) - corr(ob.U[t])).max() < 1e-9
     sim.close()
+
+
+def test_orthonormality_after_certified_second_pass():
+    """The second Cholesky-QR pass keeps U when its Gram certifies |U^+ U - I| <= 1e-13 entrywise
+    (and applies the first-order or full factor otherwise): after homodyne and projective steps
+    at weak and strong monitoring every trajectory is orthonormal to that accuracy (host check
+    adds its own rounding, about L eps)."""
+    L, B = 256, 4
+    gam = [0.05, 0.5, 2.0, 6.0]
+    sim = make_sim(1, L, n_traj=B)
+    for protocol in (QSD, PM, QSD):
+        sim.step(protocol, gam, 0.05, 3, 7)
+        U, _ = sim.get_state()
+        for t in range(B):
+            dev = np.abs(U[t].conj().T @ U[t] - np.eye(L // 2)).max()
+            assert dev <= 1e-13 + 4 * L * 2.2e-16, (protocol, t, dev)
+    sim.close()
