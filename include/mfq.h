@@ -197,6 +197,22 @@ mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double d
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out);
 
+/* Form in which exp(-i Ht dt) is applied (Appendix A free evolution).
+ *   MFQ_PROP_DENSE     the dense L x L propagator as one GEMM over the batch (default; FP32
+ *                      planes with MFQ_FP32_BULK);
+ *   MFQ_PROP_FACTORED  on a ring, a banded stencil of the generating row: entries beyond the
+ *                      band are below 1e-20 of the largest, so the result equals the dense
+ *                      product to rounding (band <= 128 and narrower than the ring, else the
+ *                      dense form is used); on a torus, the exact factors P = P_y (x) P_x
+ *                      applied as two GEMMs (P U = vec(P_x X P_y) per column, X the Lx x Ly
+ *                      view).  Always FP64.
+ * mfq_propagator_band reports the ring band w (taps -w..w; -1: none narrower than the ring,
+ * -2: torus) for the dt of the most recent step. */
+#define MFQ_PROP_DENSE 0
+#define MFQ_PROP_FACTORED 1
+mfq_status mfq_set_propagator(mfq_ctx *ctx, int32_t form);
+mfq_status mfq_propagator_band(mfq_ctx *ctx, int32_t *band);
+
 /* How projective measurements of a step are carried out (Appendix A, Eq. (A1),
  * Eq. (A2) sign-corrected).  Both forms give the same outcomes and
  * conditional probabilities from the same random numbers, and the same state

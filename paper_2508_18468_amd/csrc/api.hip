@@ -33,6 +33,11 @@ struct mfq_ctx {
   cplx *X[2] = {nullptr, nullptr};
   int cur = 0;
   cplx *P = nullptr, *gx = nullptr, *gy = nullptr;
+  // factored propagator: band of the ring stencil (1d) or the factors P_x, P_y (2d)
+  int prop_form = 0;  // MFQ_PROP_DENSE
+  int band_w = -1;    // -1: no band narrower than the ring
+  cplx *Pkx = nullptr, *Pky = nullptr;
+  int g_prop = -1;    // propagator form the cached graph was captured with
   float *Pr32 = nullptr, *Pi32 = nullptr;  // FP32-bulk: planes of P - I
   CholWork chol{};
   EigWork eig{};
@@ -114,13 +119,18 @@ struct Plan {
   }
 };
 
-void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
+void carve(Plan &pl, const mfq_lattice &lat, int L, int N, int B, int precision, mfq_ctx *c) {
   const size_t LN = (size_t)L * N, NN = (size_t)N * N;
   cplx *x0 = pl.take<cplx>(LN * B);
   cplx *x1 = pl.take<cplx>(LN * B);
   cplx *P = pl.take<cplx>((size_t)L * L);
   cplx *gx = pl.take<cplx>(L);
   cplx *gy = pl.take<cplx>(L);
+  cplx *pkx = nullptr, *pky = nullptr;  // torus: the factors P_x, P_y of the propagator
+  if (lat.dim == 2) {
+    pkx = pl.take<cplx>((size_t)lat.Lx * lat.Lx);
+    pky = pl.take<cplx>((size_t)lat.Ly * lat.Ly);
+  }
   cplx *G = pl.take<cplx>(NN * B);
   cplx *Rinv = pl.take<cplx>(NN * B);
   cplx *T = pl.take<cplx>((size_t)N * CHOL_NB * B);
@@ -154,7 +164,7 @@ void carve(Plan &pl, int L, int N, int B, int precision, mfq_ctx *c) {
   float *pi32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   if (!c) return;
   c->Pr32 = pr32; c->Pi32 = pi32;
-  c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy;
+  c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy; c->Pkx = pkx; c->Pky = pky;
   c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
   c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
   c->step_base = step_base;
@@ -257,6 +267,20 @@ mfq_status build_propagator(mfq_ctx *c, double dt) {
          "propagator row upload");
   HIPCHK(expand_propagator(c->P, c->gx, c->gy, c->lat.dim, c->lat.Lx, c->lat.Ly, c->stream),
          "expand_propagator");
+  // factored form: band of the ring row (entries beyond it are below 1e-20 of the largest,
+  // far under the rounding of the kept terms), or the two ring factors of the torus
+  c->band_w = -1;
+  if (c->lat.dim == 1) {
+    double gmax = 0.0;
+    for (auto &z : gx) gmax = std::max(gmax, std::abs(z));
+    int w = 0;
+    for (int d = 1; d <= c->lat.Lx / 2; ++d)
+      if (std::abs(gx[d]) > 1e-20 * gmax || std::abs(gx[c->lat.Lx - d]) > 1e-20 * gmax) w = d;
+    if (2 * w + 1 <= c->lat.Lx && w <= 128) c->band_w = w;
+  } else {
+    HIPCHK(expand_propagator(c->Pkx, c->gx, c->gy, 1, c->lat.Lx, 1, c->stream), "expand P_x");
+    HIPCHK(expand_propagator(c->Pky, c->gy, c->gx, 1, c->lat.Ly, 1, c->stream), "expand P_y");
+  }
   if (c->precision == MFQ_FP32_BULK)
     HIPCHK(make_delta_planes(c->P, c->Pr32, c->Pi32, c->L, c->stream), "delta planes");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
@@ -345,25 +369,54 @@ bool blocked_pm(const mfq_ctx *c) {
   return c->pm_path == MFQ_PM_AUTO && c->L >= PM_BLOCKED_MIN_L;
 }
 
-// Enqueue one step on the stream (state X[cur] -> X[1-cur]); the step index is
-// read on the device as *step_dev + step_offset.
+bool factored_propagator(const mfq_ctx *c) {
+  return c->prop_form == MFQ_PROP_FACTORED && (c->lat.dim == 2 || c->band_w >= 0);
+}
+
+// Enqueue one step on the stream; the step index is read on the device as
+// *step_dev + step_offset.  The propagated state lands in X[1-cur] (dense form,
+// ring band) or, for the torus factors, back in X[cur]; measurement and the
+// re-orthonormalisation end in the same buffer, which becomes the current one.
 mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int step_offset) {
   const int L = c->L, N = c->N, B = c->B;
   cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
-  // propagator: Xb = P Xa, the batch as one L x (N*B) matrix
-  GemmDesc g{};
-  g.M = L; g.N = N * B; g.K = L; g.batch = 1;
-  g.A = c->P; g.lda = L; g.opA = OP_N;
-  g.B = Xa; g.ldb = L; g.opB = OP_N;
-  g.D = Xb; g.ldd = L;
-  g.alpha = cplx{1.0, 0.0};
+  int pidx = 1 - c->cur;
   {
     PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
-    if (c->precision == MFQ_FP32_BULK)
+    if (factored_propagator(c) && c->lat.dim == 1) {
+      HIPCHK(ring_stencil(Xa, Xb, c->gx, L, c->band_w, (long)N * B, c->stream), "propagator band");
+    } else if (factored_propagator(c)) {
+      // P U = vec(P_x X P_y^T) column by column, X the Lx x Ly view of a column (P_y = P_y^T)
+      const int Lx = c->lat.Lx, Ly = c->lat.Ly;
+      GemmDesc g{};
+      g.alpha = cplx{1.0, 0.0};
+      g.M = Lx; g.N = Ly * N * B; g.K = Lx; g.batch = 1;
+      g.A = c->Pkx; g.lda = Lx; g.opA = OP_N;
+      g.B = Xa; g.ldb = Lx; g.opB = OP_N;
+      g.D = Xb; g.ldd = Lx;
+      HIPCHK(zgemm(g, c->stream), "propagator P_x");
+      GemmDesc h{};
+      h.alpha = cplx{1.0, 0.0};
+      h.M = Lx; h.N = Ly; h.K = Ly; h.batch = N * B;
+      h.A = Xb; h.lda = Lx; h.sA = L; h.opA = OP_N;
+      h.B = c->Pky; h.ldb = Ly; h.sB = 0; h.opB = OP_N;
+      h.D = Xa; h.ldd = Lx; h.sD = L;
+      HIPCHK(zgemm(h, c->stream), "propagator P_y");
+      pidx = c->cur;
+    } else if (c->precision == MFQ_FP32_BULK) {
       HIPCHK(propagator_delta_f32(c->Pr32, c->Pi32, Xa, Xb, L, N * B, c->stream), "propagator f32");
-    else
+    } else {  // dense: Xb = P Xa, the batch as one L x (N*B) matrix
+      GemmDesc g{};
+      g.M = L; g.N = N * B; g.K = L; g.batch = 1;
+      g.A = c->P; g.lda = L; g.opA = OP_N;
+      g.B = Xa; g.ldb = L; g.opB = OP_N;
+      g.D = Xb; g.ldd = L;
+      g.alpha = cplx{1.0, 0.0};
       HIPCHK(zgemm_propagator(g, c->stream), "propagator gemm");
+    }
   }
+  Xb = c->X[pidx];          // propagated state
+  Xa = c->X[1 - pidx];      // free buffer
   {
     PhaseTimer t(c, MFQ_PHASE_MEASURE);
     if (protocol == MFQ_HOMODYNE) {
@@ -385,7 +438,7 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
     HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, false, c->stream), "cholqr pass 1");
     HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, true, c->stream), "cholqr pass 2");
   }
-  c->cur = 1 - c->cur;
+  c->cur = pidx;
   return MFQ_OK;
 }
 
@@ -408,7 +461,7 @@ void drop_graph(mfq_ctx *c) {
 // parity change.  Replayed with hipGraphLaunch for each pair of steps.
 mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed) {
   if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur &&
-      c->g_tile == c->tile_mode)
+      c->g_tile == c->tile_mode && c->g_prop == c->prop_form)
     return MFQ_OK;
   drop_graph(c);
   const int cur0 = c->cur;
@@ -432,6 +485,7 @@ mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed)
   c->g_seed = seed;
   c->g_cur = cur0;
   c->g_tile = c->tile_mode;
+  c->g_prop = c->prop_form;
   return MFQ_OK;
 }
 
@@ -490,7 +544,7 @@ mfq_status mfq_workspace_bytes(const mfq_lattice *lat, int32_t N, int32_t n_traj
   const int L = lattice_L(lat);
   if (N < 1 || N >= L) return MFQ_EINVAL;
   Plan pl;
-  carve(pl, L, N, n_traj, precision, nullptr);
+  carve(pl, *lat, L, N, n_traj, precision, nullptr);
   *bytes = pl.off + 256;
   return MFQ_OK;
 }
@@ -527,7 +581,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   }
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MFQ_EDEVICE, "hipSetDevice");
   Plan sizing;
-  carve(sizing, L, N, n_traj, precision, nullptr);
+  carve(sizing, *lat, L, N, n_traj, precision, nullptr);
   const size_t need = sizing.off + 256;
   if (c->own_ws && c->ws) {
     (void)hipStreamSynchronize(c->stream);
@@ -550,7 +604,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   drop_graph(c);
   Plan pl;
   pl.base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws)));
-  carve(pl, L, N, n_traj, precision, c);
+  carve(pl, *lat, L, N, n_traj, precision, c);
   c->lat = *lat;
   c->L = L; c->N = N; c->B = n_traj; c->precision = precision;
   c->step = 0; c->cur = 0; c->dt_cached = NAN;
@@ -591,6 +645,22 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
   }
   c->step += n_steps;
+  return MFQ_OK;
+}
+
+mfq_status mfq_set_propagator(mfq_ctx *c, int32_t form) {
+  if (!c) return MFQ_EINVAL;
+  if (form != MFQ_PROP_DENSE && form != MFQ_PROP_FACTORED)
+    return fail(c, MFQ_EINVAL, "unknown propagator form");
+  c->prop_form = form;
+  drop_graph(c);
+  return MFQ_OK;
+}
+
+mfq_status mfq_propagator_band(mfq_ctx *c, int32_t *band) {
+  if (!c || !band) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  *band = c->lat.dim == 1 ? c->band_w : -2;
   return MFQ_OK;
 }
 

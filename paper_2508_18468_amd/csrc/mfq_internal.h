@@ -77,6 +77,9 @@ hipError_t propagator_delta_f32(const float *Pr, const float *Pi, const cplx *U,
 hipError_t expand_propagator(cplx *P, const cplx *gx, const cplx *gy, int dim, int Lx, int Ly,
                              hipStream_t s);
 hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t s);
+// D = P U for the ring propagator P_ab = g[(a - b) mod L] truncated to |a - b| <= w (band);
+// U and D are column-major L x ncols and must not overlap; 2 w + 1 <= L, w <= 128.
+hipError_t ring_stencil(const cplx *U, cplx *D, const cplx *g, int L, int w, long ncols, hipStream_t s);
 // The absolute step index n of a step is read on the device as *step_ptr + step_offset,
 // so that a captured graph of steps can be replayed unchanged.
 hipError_t set_step(int64_t *step_ptr, int64_t value, bool add, hipStream_t s);

@@ -130,6 +130,36 @@ __global__ __launch_bounds__(256) void born_rows_kernel(cplx *U, double *p, int 
   }
 }
 
+// Banded ring propagator: D[a, c] = sum_{|d| <= w} g[d mod L] U[(a - d) mod L, c], the
+// circulant exp(-i Ht dt) with the generating-row entries beyond distance w dropped (the
+// caller picks w so that they are below the rounding of the kept ones).  One workgroup per
+// (256-row block, column): the rows it needs, with a halo of w on each side, go through LDS.
+constexpr int STENCIL_WMAX = 128;
+__global__ __launch_bounds__(256) void ring_stencil_kernel(const cplx *U, cplx *D, const cplx *g, int L,
+                                                           int w, int nrb) {
+  __shared__ cplx s[256 + 2 * STENCIL_WMAX];
+  const long id = blockIdx.x;
+  const int rb = (int)(id % nrb);
+  const long c = id / nrb;
+  const int r0 = rb * 256;
+  const cplx *Uc = U + c * L;
+  for (int t = threadIdx.x; t < 256 + 2 * w; t += 256) {
+    int r = (r0 - w + t) % L;
+    if (r < 0) r += L;
+    s[t] = Uc[r];
+  }
+  __syncthreads();
+  const int i = r0 + threadIdx.x;
+  if (i >= L) return;
+  double ar = 0.0, ai = 0.0;
+  for (int d = -w; d <= w; ++d) {
+    const cplx gd = g[d < 0 ? d + L : d], u = s[threadIdx.x + w - d];
+    ar += gd.re * u.re - gd.im * u.im;
+    ai += gd.re * u.im + gd.im * u.re;
+  }
+  D[c * L + i] = cplx{ar, ai};
+}
+
 // Projective measurement of one step, one trajectory per workgroup (see
 // pm_measure_block).
 __global__ __launch_bounds__(256) void pm_kernel(cplx *U, int L, int N, const double *gamma,
@@ -203,6 +233,13 @@ hipError_t init_state(cplx *U, int L, int N, int B, const int *occ, hipStream_t 
   const long total = (long)L * N * B;
   const int blocks = (int)std::min<long>((total + 255) / 256, 65536);
   hipLaunchKernelGGL(init_state_kernel, dim3(blocks), dim3(256), 0, s, U, L, N, total, occ);
+  return hipGetLastError();
+}
+
+hipError_t ring_stencil(const cplx *U, cplx *D, const cplx *g, int L, int w, long ncols, hipStream_t s) {
+  if (w < 0 || w > STENCIL_WMAX || 2 * w + 1 > L) return hipErrorInvalidValue;
+  const int nrb = (L + 255) / 256;
+  hipLaunchKernelGGL(ring_stencil_kernel, dim3((unsigned)(nrb * ncols)), dim3(256), 0, s, U, D, g, L, w, nrb);
   return hipGetLastError();
 }
 

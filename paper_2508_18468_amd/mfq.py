@@ -89,6 +89,8 @@ _SIGS = {
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_set_propagator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_propagator_band": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_particle_covariance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_reset_trajectory": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64]),
@@ -283,6 +285,19 @@ def mfq_set_tuning(ctx, path, tile):
     _check(ctx, lib().mfq_set_tuning(ctx, int(path), int(tile)))
 
 
+PROP_DENSE, PROP_FACTORED = 0, 1
+
+
+def mfq_set_propagator(ctx, form):
+    _check(ctx, lib().mfq_set_propagator(ctx, int(form)))
+
+
+def mfq_propagator_band(ctx):
+    w = ctypes.c_int32()
+    _check(ctx, lib().mfq_propagator_band(ctx, ctypes.byref(w)))
+    return w.value
+
+
 PM_AUTO, PM_WORKGROUP, PM_BLOCKED = 0, 1, 2
 
 
@@ -450,6 +465,12 @@ class Trajectories:
 
     def set_pm_path(self, path):
         mfq_set_pm_path(self.ctx, path)
+
+    def set_propagator(self, form):
+        mfq_set_propagator(self.ctx, form)
+
+    def propagator_band(self):
+        return mfq_propagator_band(self.ctx)
 
     def autotune(self, protocol, gamma, dt, seed, probe_steps=4, cache=None):
         """Tune the execution form (mfq_autotune) or reuse a choice cached in the JSON file
