@@ -196,7 +196,7 @@ def run_large(args):
     out = {"metric": "L*N*steps/s", "value": B * w.L * w.N * steps / T, "unit": "L*N*steps/s",
            "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": T / steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if precision == mfq.FP64 else "f64 (propagator f32)", "data": "synthetic",
+           "dtype": "f64" if (precision == mfq.FP64 or factored) else "f64 (propagator f32)", "data": "synthetic",
            "config": {"workload": w.name, "L": w.L, "N": w.N, "n_traj": B, "propagator": args.propagator,
                       "band": band if factored and w.dim == 1 else None,
                       "gammas": list(w.gammas), "protocol": "projective" if w.protocol == 0 else "homodyne",
