@@ -18,6 +18,7 @@ dynamics of monitored noninteracting fermions on graphics processing units":
 * entanglement entropy                  -- Sec. II, entropy formula
 * mutual information                    -- Sec. IV
 * density correlation C(r), G_AB        -- Sec. II Eq. (2), Sec. IV Eq. (5)
+* continuous-time projective protocol   -- Appendix A (Poisson waiting times, one site per event)
 
 Random numbers: Philox4x64-10 (Salmon et al., SC'11), implemented here from
 its published definition, independently of the GPU's implementation.
@@ -35,6 +36,8 @@ from .trajectory import (initial_state, propagate, born_probabilities,
 from .observables import (correlation_matrix, region_spectrum, entropy_from_spectrum,
                           entanglement_entropy, mutual_information, density_correlation,
                           particle_covariance)
+from .continuous import (event_draws, waiting_time, evolution_operator, evolve, measure_site,
+                         state_from_correlation, run_continuous)
 
 __all__ = [
     "Lattice", "hopping_matrix", "default_occupied", "propagator",
@@ -43,4 +46,6 @@ __all__ = [
     "reorthonormalize", "step", "run_trajectory",
     "correlation_matrix", "region_spectrum", "entropy_from_spectrum",
     "entanglement_entropy", "mutual_information", "density_correlation", "particle_covariance",
+    "event_draws", "waiting_time", "evolution_operator", "evolve", "measure_site",
+    "state_from_correlation", "run_continuous",
 ]

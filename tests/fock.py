@@ -61,6 +61,22 @@ class FockSim:
         w, V = np.linalg.eigh(self.H)
         self.E = (V * np.exp(-1j * w * dt)[None, :]) @ np.conj(V.T)
 
+    def evolve(self, tau):
+        """psi <- exp(-i H tau) psi for any tau (many-body eigendecomposition)."""
+        if not hasattr(self, "_eig"):
+            self._eig = np.linalg.eigh(self.H)
+        w, V = self._eig
+        self.psi = V @ (np.exp(-1j * w * tau) * (np.conj(V.T) @ self.psi))
+
+    def measure(self, j, p_c):
+        """Projective measurement of n_j: outcome 1 iff p_c <= <n_j>; projector, renormalise."""
+        p = float((np.abs(self.psi) ** 2) @ self.occ[:, j])
+        outcome = 1 if p_c <= p else 0
+        mask = self.occ[:, j] if outcome == 1 else 1.0 - self.occ[:, j]
+        self.psi = self.psi * mask
+        self.psi /= np.linalg.norm(self.psi)
+        return p, outcome
+
     def occupations(self):
         return (np.abs(self.psi) ** 2) @ self.occ
 
