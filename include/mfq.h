@@ -170,6 +170,43 @@ mfq_status mfq_occupations(mfq_ctx *ctx, double *p_host);
 mfq_status mfq_pm_events(mfq_ctx *ctx, int32_t max_events, int32_t *counts, int32_t *sites,
                          int32_t *outcomes, double *probs);
 
+/* Continuous-time projective protocol (Appendix A, PM protocol with Poisson waiting times).
+ * Runs n_events event slots.  In each slot every trajectory t whose clock is below t_end
+ * takes one event:
+ *   tau = -ln(eta) / (gamma[t] N), eta uniform in (0, 1), N the particle number (the total
+ *     event rate is gamma N, the per-site rate gamma N / L); the clock advances by tau;
+ *   U <- exp(-i Ht tau) U, exact for every tau: the ring row of Bessel terms
+ *     (-i)^|n| J_|n|(2 J tau) kept while above 1e-20 of the largest (or, when the band
+ *     would wrap, the full row from its plane-wave sum); on the torus P_y (x) P_x;
+ *   a site j uniform over the L sites, p_j = <n_j>, outcome 1 iff p_c <= p_j with p_c
+ *     uniform, and the exact projection of the Slater determinant (Eq. (A1); Eq. (A2)
+ *     with the sign of its rank-1 term corrected).
+ * Trajectories whose clock has reached t_end (t_end = +inf: never) keep their state.
+ * Random numbers: Philox4x64-10, key (seed, uid), counter (n, 0, 2, 0) with n the
+ * trajectory's own step index (shared with mfq_step; each slot advances it by one);
+ * word 0 -> eta, word 1 -> j = high 64 bits of word1 * L, word 2 -> p_c.
+ * gamma: n_traj host doubles, each > 0.  reorth_every = R > 0: both Cholesky-QR passes
+ * after every slot whose absolute step index is a multiple of R (0: never; each event
+ * is exactly unitary up to rounding).  Asynchronous (stream-ordered).
+ * Errors: MFQ_EINVAL (gamma NULL or not positive and finite, n_events < 0, t_end NaN,
+ * reorth_every < 0), MFQ_ESTATE, MFQ_EDEVICE. */
+mfq_status mfq_ct_events(mfq_ctx *ctx, const double *gamma, uint64_t seed, int32_t n_events,
+                         double t_end, int32_t reorth_every);
+
+/* Record of the latest event slot of mfq_ct_events, per trajectory t (host arrays of
+ * n_traj entries, any may be NULL): measured site, outcome (0/1), Born probability p_j
+ * and waiting time tau; site = outcome = -1 and p = tau = 0 where the trajectory took
+ * no event (or no slot has run since mfq_init_state).  Synchronises. */
+mfq_status mfq_ct_last_events(mfq_ctx *ctx, int32_t *site, int32_t *outcome, double *prob,
+                              double *tau);
+
+/* Clocks of the continuous-time protocol (t_host: n_traj host doubles).  They start at 0
+ * in mfq_init_state and mfq_reset_trajectory and advance only in mfq_ct_events.
+ * mfq_set_times restores them (finite values) with a checkpoint.  Both synchronise.
+ * Errors: MFQ_EINVAL (NULL, non-finite), MFQ_ESTATE, MFQ_EDEVICE. */
+mfq_status mfq_get_times(mfq_ctx *ctx, double *t_host);
+mfq_status mfq_set_times(mfq_ctx *ctx, const double *t_host);
+
 /* Checkpoint: copy the current U of all trajectories (L*N*n_traj complex
  * doubles, layout as above) to host memory and report the absolute step
  * index.  Synchronises. */

@@ -49,6 +49,8 @@ struct mfq_ctx {
   cplx *pm_v = nullptr, *pm_w = nullptr;
   PmBlockedWork pmb{};
   int pm_path = 0;  // MFQ_PM_AUTO
+  ContWork ct{};    // continuous-time protocol: clocks, ring rows, event records
+  bool ct_any = false;  // an event batch has run since mfq_init_state
   std::vector<double> gamma_host;
   // phase timing
   bool profiling = false;
@@ -160,6 +162,15 @@ void carve(Plan &pl, const mfq_lattice &lat, int L, int N, int B, int precision,
   double *elam = pl.take<double>((size_t)N * B);
   double *eS = pl.take<double>(B);
   int64_t *step_base = pl.take<int64_t>(B);
+  const int Lyr = lat.dim == 2 ? lat.Ly : 1, jcap = cont_jcap(lat.Lx, Lyr);
+  double *ct_t = pl.take<double>(B);
+  cplx *ct_g = pl.take<cplx>((size_t)(lat.Lx + Lyr) * B);
+  double *ct_jn = pl.take<double>((size_t)jcap * B);
+  int *ct_info = pl.take<int>((size_t)4 * B);
+  double *ct_dinfo = pl.take<double>((size_t)4 * B);
+  cplx *ct_v = pl.take<cplx>((size_t)N * B);
+  cplx *ct_y = pl.take<cplx>((size_t)L * B);
+  cplx *ct_yp = pl.take<cplx>((size_t)L * B);
   float *pr32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   float *pi32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
   if (!c) return;
@@ -174,6 +185,7 @@ void carve(Plan &pl, const mfq_lattice &lat, int L, int N, int B, int precision,
   c->pm_v = pm_v; c->pm_w = pm_w;
   c->pmb = PmBlockedWork{pm_sites, pm_out, pm_cnt, pm_prob, pm_u, pm_tau, pm_m1, pm_k1, pm_code,
                          G, Rinv, T};
+  c->ct = ContWork{ct_t, ct_g, ct_jn, ct_info, ct_dinfo, ct_v, ct_y, ct_yp, jcap};
 }
 
 // Generating row of the ring propagator exp(-i Ht dt) from the Jacobi-Anger
@@ -607,7 +619,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   carve(pl, *lat, L, N, n_traj, precision, c);
   c->lat = *lat;
   c->L = L; c->N = N; c->B = n_traj; c->precision = precision;
-  c->step = 0; c->cur = 0; c->dt_cached = NAN;
+  c->step = 0; c->cur = 0; c->dt_cached = NAN; c->ct_any = false;
   c->gamma_host.assign(n_traj, -1.0);
   HIPCHK(hipMemcpyAsync(c->uid, traj_uid, n_traj * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream),
          "uid upload");
@@ -616,6 +628,8 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
   HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
   HIPCHK(fill_zero(c->pm_cnt, ((size_t)n_traj * sizeof(int) + 7) / 8 * 8, c->stream), "event clear");
   HIPCHK(fill_zero(c->step_base, (size_t)n_traj * sizeof(int64_t), c->stream), "step base clear");
+  HIPCHK(cont_clock_set(c->ct.t, 0, n_traj, 0.0, c->stream), "clock clear");
+  HIPCHK(fill_zero(c->ct.info, (size_t)4 * n_traj * sizeof(int), c->stream), "event record clear");
   HIPCHK(init_state(c->X[0], L, N, n_traj, c->occ, c->stream), "init_state");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   c->ready = true;
@@ -645,6 +659,98 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
     HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
   }
   c->step += n_steps;
+  return MFQ_OK;
+}
+
+mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t n_events, double t_end,
+                         int32_t reorth_every) {
+  if (!c) return MFQ_EINVAL;
+  TileScope tiles(c);
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!gamma) return fail(c, MFQ_EINVAL, "gamma is NULL");
+  for (int b = 0; b < c->B; ++b)
+    if (!(gamma[b] > 0.0) || !std::isfinite(gamma[b]))
+      return fail(c, MFQ_EINVAL, "gamma must be positive and finite");
+  if (n_events < 0) return fail(c, MFQ_EINVAL, "n_events < 0");
+  if (std::isnan(t_end)) return fail(c, MFQ_EINVAL, "t_end is NaN");
+  if (reorth_every < 0) return fail(c, MFQ_EINVAL, "reorth_every < 0");
+  if (n_events == 0) return MFQ_OK;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  if (std::memcmp(c->gamma_host.data(), gamma, c->B * sizeof(double)) != 0) {
+    std::memcpy(c->gamma_host.data(), gamma, c->B * sizeof(double));
+    HIPCHK(hipMemcpyAsync(c->gamma, c->gamma_host.data(), c->B * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream), "gamma upload");
+  }
+  HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
+  const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+  for (int e = 0; e < n_events; ++e) {
+    bool in_b = false;
+    {
+      PhaseTimer t(c, MFQ_PHASE_MEASURE);
+      HIPCHK(cont_event(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->lat.dim, c->lat.Lx, Ly,
+                        c->lat.J, c->gamma, t_end, seed, c->uid, c->step_dev, 1, c->step_base, c->ct,
+                        &in_b, c->stream), "continuous-time event");
+    }
+    if (in_b) c->cur = 1 - c->cur;
+    HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
+    c->step += 1;
+    c->ct_any = true;
+    if (reorth_every > 0 && c->step % reorth_every == 0) {
+      PhaseTimer t(c, MFQ_PHASE_REORTH);
+      HIPCHK(cholqr_pass(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, false, c->stream),
+             "cholqr pass 1");
+      HIPCHK(cholqr_pass(c->X[1 - c->cur], c->X[c->cur], c->L, c->N, c->B, c->chol, true, c->stream),
+             "cholqr pass 2");
+    }
+  }
+  return MFQ_OK;
+}
+
+mfq_status mfq_ct_last_events(mfq_ctx *c, int32_t *site, int32_t *outcome, double *prob, double *tau) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  const int B = c->B;
+  std::vector<int> info((size_t)4 * B);
+  std::vector<double> dinfo((size_t)4 * B);
+  if (c->ct_any) {
+    HIPCHK(hipMemcpyAsync(info.data(), c->ct.info, info.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream), "event record download");
+    HIPCHK(hipMemcpyAsync(dinfo.data(), c->ct.dinfo, dinfo.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream), "event record download");
+    HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  }
+  for (int b = 0; b < B; ++b) {
+    const bool ev = c->ct_any && info[4 * b + 2] >= 0;
+    if (site) site[b] = ev ? info[4 * b] : -1;
+    if (outcome) outcome[b] = ev ? info[4 * b + 1] : -1;
+    if (prob) prob[b] = ev ? dinfo[4 * b + 1] : 0.0;
+    if (tau) tau[b] = ev ? dinfo[4 * b] : 0.0;
+  }
+  return check_flag(c);
+}
+
+mfq_status mfq_get_times(mfq_ctx *c, double *t_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!t_host) return fail(c, MFQ_EINVAL, "t_host is NULL");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(t_host, c->ct.t, c->B * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "clock download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return check_flag(c);
+}
+
+mfq_status mfq_set_times(mfq_ctx *c, const double *t_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!t_host) return fail(c, MFQ_EINVAL, "t_host is NULL");
+  for (int b = 0; b < c->B; ++b)
+    if (!std::isfinite(t_host[b])) return fail(c, MFQ_EINVAL, "clock values must be finite");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(c->ct.t, t_host, c->B * sizeof(double), hipMemcpyHostToDevice, c->stream),
+         "clock upload");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   return MFQ_OK;
 }
 
@@ -944,6 +1050,7 @@ mfq_status mfq_reset_trajectory(mfq_ctx *c, int32_t slot, uint64_t uid) {
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");
   HIPCHK(reset_slot(c->X[c->cur], c->L, c->N, slot, c->occ, c->uid, uid, c->step_base, c->step, c->stream),
          "reset slot");
+  HIPCHK(cont_clock_set(c->ct.t, slot, 1, 0.0, c->stream), "clock reset");
   return MFQ_OK;
 }
 

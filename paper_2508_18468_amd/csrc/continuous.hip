@@ -1,0 +1,458 @@
+// Continuous-time projective protocol (Appendix A, PM protocol): one event per
+// active trajectory and launch sequence.
+//
+// An event of trajectory b: waiting time tau = -ln(eta) / (gamma N), U <- P(tau) U
+// with P(tau) = exp(-i H tau), a site j uniform over the L sites, p_j = |row j of U|^2,
+// outcome 1 iff p_c <= p_j, and the exact projection of the Slater determinant
+// (a Householder reflector confines row j to column 0; column 0 becomes e_j for
+// outcome 1, or loses its row-j entry and is renormalised for outcome 0).  This is
+// Eq. (A1) / Eq. (A2) (sign of its rank-1 term corrected) on C = U U^+, done on U.
+//
+// Launches per event:
+//   cont_draw_kernel   one workgroup per trajectory: draws, clock, the ring rows
+//                      of P(tau) (Bessel band or plane-wave sum), row j of P U,
+//                      Born decision and the reflector v (H = I - tau_h v v^+)
+//   cont_gemv_kernel   y = tau_h U v                         (reads U once)
+//   cont_prop_kernel   yp = P(tau) y                         (vectors only)
+//   cont_apply_kernel  U' = P(tau) U - yp v^+, row j / column 0 fixed
+//                      (reads U once, writes U' once; on the torus the x factor
+//                      runs first in a plain pass, the y factor with the update)
+//   cont_norm_kernel   outcome 0: column 0 renormalised      (column 0 only)
+//
+// P(tau) on the ring is the circulant with generating row
+// g[d] = sum over integers n = d (mod L) of (-i)^|n| J_|n|(2 J tau) (Jacobi-Anger);
+// on the torus P = P_y (x) P_x with the rows of both rings.  While the Bessel
+// terms beyond order M fall below 1e-20 of the largest and 2 M + 1 <= L, the row
+// is the band |d| <= w (taps below that bound dropped); otherwise the full row
+// comes from its plane-wave sum (1/L) sum_m exp(-i z cos k_m + i k_m d).
+#include <cmath>
+
+#include "mfq_internal.h"
+#include "device_common.h"
+
+namespace mfq {
+
+namespace {
+
+constexpr double BAND_REL = 1e-20;
+
+// Taps of one ring direction: band |d| <= w, or the whole ring (w >= period).
+struct Taps {
+  int lo, hi;
+};
+__device__ __forceinline__ Taps taps_of(int w, int period) {
+  if (w < 0) return Taps{0, 0};                 // no event: identity
+  if (w >= period) return Taps{0, period - 1};  // full ring
+  return Taps{-w, w};
+}
+
+__device__ __forceinline__ int wrap(int a, int p) {
+  a %= p;
+  return a < 0 ? a + p : a;
+}
+
+// Smallest order M beyond which |J_n(x)| < BAND_REL max|J| for x = |z|: the
+// transition region of J_n(x) around n = x is O(x^(1/3)) wide and the decay past
+// it is faster than exp(-(n - x)^(3/2) / x^(1/2)); for x <= 1 the series
+// (x/2)^n / n! is below 1e-20 by n = 25.
+__device__ __forceinline__ int bessel_order_bound(double x) {
+  return (int)ceil(x + 15.0 * cbrt(x) + 25.0);
+}
+
+// Miller's backward recurrence J_{n-1} = (2n/x) J_n - J_{n+1} from order ms down
+// to 0 (J_{ms+1} = 0, J_ms = tiny), normalised by J_0 + 2 sum_k J_2k = 1.  The
+// recurrence is stable for the decaying solution J_n in this direction; values are
+// rescaled by 1e-250 whenever one exceeds 1e250 (for x >= 1e-50 one step grows a value
+// by at most 2 ms / x < 1e55, so nothing overflows).  Writes jn[0..ms].
+__device__ void bessel_miller(double x, int ms, double *jn) {
+  double up = 0.0, cur = 1e-300;
+  jn[ms] = cur;
+  for (int n = ms; n >= 1; --n) {
+    const double nxt = (2.0 * n / x) * cur - up;
+    up = cur;
+    cur = nxt;
+    jn[n - 1] = nxt;
+    if (fabs(nxt) > 1e250) {
+      for (int k = n - 1; k <= ms; ++k) jn[k] *= 1e-250;
+      up *= 1e-250;
+      cur *= 1e-250;
+    }
+  }
+  double sum = jn[0];
+  for (int k = 2; k <= ms; k += 2) sum += 2.0 * jn[k];
+  const double inv = 1.0 / sum;
+  for (int k = 0; k <= ms; ++k) jn[k] *= inv;
+}
+
+// Ring row of P(tau) for one direction (period Lr) into g[0..Lr); returns the band
+// w (w >= Lr: full ring).  Called by the whole workgroup; thread 0 runs the
+// recurrence.  z = 2 J tau (any sign: J_n(-x) = (-1)^n J_n(x)).
+__device__ int ring_row_dev(double z, int Lr, cplx *g, double *jn, int jcap, int *sh_w) {
+  const int tid = threadIdx.x;
+  const double x = fabs(z);
+  if (x < 1e-50) {  // J_1(x) < 1e-50: the identity to far below rounding
+    if (tid == 0) g[0] = cplx{1.0, 0.0};
+    __syncthreads();
+    return 0;
+  }
+  const int M = bessel_order_bound(x);
+  const int ms = M + (int)ceil(sqrt(160.0 * (M + 1))) + 20;
+  const bool band = 2 * M + 1 <= Lr && ms + 1 <= jcap;
+  if (band) {
+    if (tid == 0) {
+      bessel_miller(x, ms, jn);
+      double mx = 0.0;
+      for (int n = 0; n <= M; ++n) mx = fmax(mx, fabs(jn[n]));
+      int w = 0;
+      for (int n = 1; n <= M; ++n)
+        if (fabs(jn[n]) > BAND_REL * mx) w = n;
+      *sh_w = w;
+    }
+    __syncthreads();
+    const int w = *sh_w;
+    for (int d = -w + tid; d <= w; d += blockDim.x) {
+      const int n = d < 0 ? -d : d;
+      double v = jn[n];
+      if (z < 0.0 && (n & 1)) v = -v;
+      cplx ph;
+      switch (n & 3) {  // (-i)^n
+        case 0: ph = cplx{v, 0.0}; break;
+        case 1: ph = cplx{0.0, -v}; break;
+        case 2: ph = cplx{-v, 0.0}; break;
+        default: ph = cplx{0.0, v}; break;
+      }
+      g[wrap(d, Lr)] = ph;
+    }
+    __syncthreads();
+    return w;
+  }
+  // full ring: g[d] = (1/Lr) sum_m exp(-i z cos k_m) exp(i k_m d), the integer
+  // product m d reduced modulo Lr before it becomes an angle
+  const double two_pi = 6.283185307179586;
+  for (int d = tid; d < Lr; d += blockDim.x) {
+    double ar = 0.0, ai = 0.0;
+    for (int m = 0; m < Lr; ++m) {
+      const double km = two_pi * m / Lr;
+      const double th = two_pi * (double)(((long)m * d) % Lr) / Lr - z * cos(km);
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      ar += cs;
+      ai += sn;
+    }
+    g[d] = cplx{ar / Lr, ai / Lr};
+  }
+  __syncthreads();
+  return Lr;
+}
+
+struct DrawArgs {
+  const cplx *U;
+  int L, N, dim, Lx, Ly;
+  double J;
+  const double *gamma;
+  double t_end;
+  uint64_t seed;
+  const uint64_t *uid;
+  const int64_t *step_ptr;
+  int step_offset;
+  const int64_t *step_base;
+  ContWork w;
+};
+
+__global__ __launch_bounds__(256) void cont_draw_kernel(DrawArgs a) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int L = a.L, N = a.N, Lx = a.Lx, Ly = a.Ly;
+  int *info = a.w.info + 4 * b;
+  double *dinfo = a.w.dinfo + 4 * b;
+  const double t0 = a.w.t[b];
+  if (!(t0 < a.t_end)) {  // the trajectory has reached the end time: no event
+    if (tid == 0) {
+      info[0] = -1; info[1] = 0; info[2] = -1; info[3] = -1;
+      dinfo[0] = 0.0; dinfo[1] = 0.0; dinfo[2] = 0.0;
+    }
+    return;
+  }
+  __shared__ double sh_tau, sh_pc, red[4];
+  __shared__ int sh_j, sh_w;
+  if (tid == 0) {
+    const uint64_t n = (uint64_t)(*a.step_ptr + a.step_offset - a.step_base[b]);
+    const u64x4 r = philox4x64_10(a.seed, a.uid[b], n, 0, PURPOSE_CONTINUOUS, 0);
+    sh_tau = -log(u01(r.v[0])) / (a.gamma[b] * N);
+    sh_j = (int)__umul64hi(r.v[1], (uint64_t)L);
+    sh_pc = u01(r.v[2]);
+  }
+  __syncthreads();
+  const double tau = sh_tau;
+  const int j = sh_j;
+  cplx *gx = a.w.g + (long)b * (Lx + Ly);
+  cplx *gy = gx + Lx;
+  double *jn = a.w.jn + (long)b * a.w.jcap;
+  const double z = 2.0 * a.J * tau;
+  const int wx = ring_row_dev(z, Lx, gx, jn, a.w.jcap, &sh_w);
+  int wy = 0;
+  if (a.dim == 2) {
+    wy = ring_row_dev(z, Ly, gy, jn, a.w.jcap, &sh_w);
+  } else if (tid == 0) {
+    gy[0] = cplx{1.0, 0.0};
+  }
+  __syncthreads();
+  // x = conj(row j of P U), p = |x|^2
+  const Taps tx = taps_of(wx, Lx), ty = taps_of(a.dim == 2 ? wy : 0, Ly);
+  const int xj = j % Lx, yj = j / Lx;
+  const cplx *Ub = a.U + (long)b * L * N;
+  cplx *v = a.w.v + (long)b * N;
+  double part = 0.0, mx = 0.0;
+  for (int k = tid; k < N; k += 256) {
+    const cplx *Uk = Ub + (long)k * L;
+    double ar = 0.0, ai = 0.0;
+    for (int dy = ty.lo; dy <= ty.hi; ++dy) {
+      const cplx gyv = gy[wrap(dy, Ly)];
+      const int row = Lx * wrap(yj - dy, Ly);
+      double sr = 0.0, si = 0.0;
+      for (int dx = tx.lo; dx <= tx.hi; ++dx) {
+        const cplx gv = gx[wrap(dx, Lx)], u = Uk[row + wrap(xj - dx, Lx)];
+        sr += gv.re * u.re - gv.im * u.im;
+        si += gv.re * u.im + gv.im * u.re;
+      }
+      ar += gyv.re * sr - gyv.im * si;
+      ai += gyv.re * si + gyv.im * sr;
+    }
+    v[k] = cplx{ar, -ai};
+    part += ar * ar + ai * ai;
+    mx = fmax(mx, fmax(fabs(ar), fabs(ai)));
+  }
+  const double p = block_sum256(part, red);
+  const double s = block_max256(mx, red);
+  double part2 = 0.0;
+  if (s >= REFLECT_TINY) {
+    const double inv = 1.0 / s;
+    for (int k = tid; k < N; k += 256) {
+      const cplx q{v[k].re * inv, v[k].im * inv};
+      v[k] = q;
+      if (k >= 1) part2 += q.re * q.re + q.im * q.im;
+    }
+  }
+  const double tail2 = block_sum256(part2, red);
+  if (tid == 0) {
+    double tau_h = 0.0;
+    if (s >= REFLECT_TINY) {
+      const Reflector h = make_reflector(v[0], tail2, s);
+      v[0] = h.v0;
+      tau_h = h.tau;
+    }
+    info[0] = j;
+    info[1] = (sh_pc <= p) ? 1 : 0;
+    info[2] = wx;
+    info[3] = a.dim == 2 ? wy : 0;
+    dinfo[0] = tau;
+    dinfo[1] = p;
+    dinfo[2] = tau_h;
+    a.w.t[b] = t0 + tau;
+  }
+}
+
+// y = tau_h U v: 64 rows per workgroup (one per lane), the four waves split the
+// columns and their partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void cont_gemv_kernel(const cplx *U, int L, int N, ContWork w) {
+  const int b = blockIdx.y;
+  if (w.info[4 * b + 2] < 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  __shared__ double sr[4][64], si[4][64];
+  double ar = 0.0, ai = 0.0;
+  if (i < L) {
+    const cplx *Ub = U + (long)b * L * N;
+    const cplx *v = w.v + (long)b * N;
+    for (int k = wave; k < N; k += 4) {
+      const cplx u = Ub[i + (long)k * L], vk = v[k];
+      ar += u.re * vk.re - u.im * vk.im;
+      ai += u.re * vk.im + u.im * vk.re;
+    }
+  }
+  sr[wave][lane] = ar;
+  si[wave][lane] = ai;
+  __syncthreads();
+  if (wave == 0 && i < L) {
+    const double th = w.dinfo[4 * b + 2];
+    const double yr = (sr[0][lane] + sr[1][lane]) + (sr[2][lane] + sr[3][lane]);
+    const double yi = (si[0][lane] + si[1][lane]) + (si[2][lane] + si[3][lane]);
+    w.y[(long)b * L + i] = cplx{th * yr, th * yi};
+  }
+}
+
+// yp = P(tau) y (both ring factors).
+__global__ __launch_bounds__(256) void cont_prop_kernel(int L, int Lx, int Ly, ContWork w) {
+  const int b = blockIdx.y;
+  const int *info = w.info + 4 * b;
+  if (info[2] < 0) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= L) return;
+  const cplx *gx = w.g + (long)b * (Lx + Ly), *gy = gx + Lx;
+  const cplx *y = w.y + (long)b * L;
+  const Taps tx = taps_of(info[2], Lx), ty = taps_of(info[3], Ly);
+  const int xi = i % Lx, yi = i / Lx;
+  double ar = 0.0, ai = 0.0;
+  for (int dy = ty.lo; dy <= ty.hi; ++dy) {
+    const cplx gyv = gy[wrap(dy, Ly)];
+    const int row = Lx * wrap(yi - dy, Ly);
+    double sr = 0.0, si = 0.0;
+    for (int dx = tx.lo; dx <= tx.hi; ++dx) {
+      const cplx gv = gx[wrap(dx, Lx)], u = y[row + wrap(xi - dx, Lx)];
+      sr += gv.re * u.re - gv.im * u.im;
+      si += gv.re * u.im + gv.im * u.re;
+    }
+    ar += gyv.re * sr - gyv.im * si;
+    ai += gyv.re * si + gyv.im * sr;
+  }
+  w.yp[(long)b * L + i] = cplx{ar, ai};
+}
+
+// One ring factor of P(tau) applied along a direction of the lattice: site i has
+// coordinate c = (i / stride) % period along it, and the tap d reads site
+// i + stride ((c - d) mod period - c).  UPDATE: also subtract yp v^+ and fix row j
+// and column 0 (the last factor of the event).  64 rows x 16 columns per
+// workgroup: lane = row, each wave 4 columns; every load is 64 consecutive rows of
+// one column except where a tap wraps around the ring.
+constexpr int CONT_CPW = 4;
+template <bool UPDATE>
+__global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D, int L, int N, int stride,
+                                                         int period, int g_off, int band_slot, int nrb,
+                                                         int Lx, int Ly, ContWork w) {
+  const int b = blockIdx.y;
+  const int rb = blockIdx.x % nrb, cb = blockIdx.x / nrb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = rb * 64 + lane;
+  const int k0 = cb * (4 * CONT_CPW) + wave * CONT_CPW;
+  if (i >= L || k0 >= N) return;
+  const int *info = w.info + 4 * b;
+  const int band = info[band_slot];
+  const cplx *g = w.g + (long)b * (Lx + Ly) + g_off;
+  const Taps t = taps_of(band, period);
+  const cplx *Ub = U + (long)b * L * N;
+  cplx *Db = D + (long)b * L * N;
+  const int c = (i / stride) % period;
+  const int base = i - stride * c;
+  const int nk = min(CONT_CPW, N - k0);
+  double ar[CONT_CPW], ai[CONT_CPW];
+#pragma unroll
+  for (int q = 0; q < CONT_CPW; ++q) ar[q] = ai[q] = 0.0;
+  if (band < 0) {  // no event: copy
+#pragma unroll
+    for (int q = 0; q < CONT_CPW; ++q)
+      if (q < nk) {
+        const cplx u = Ub[i + (long)(k0 + q) * L];
+        ar[q] = u.re;
+        ai[q] = u.im;
+      }
+  } else {
+    for (int d = t.lo; d <= t.hi; ++d) {
+      const cplx gv = g[wrap(d, period)];
+      const long src = base + (long)stride * wrap(c - d, period);
+#pragma unroll
+      for (int q = 0; q < CONT_CPW; ++q)
+        if (q < nk) {
+          const cplx u = Ub[src + (long)(k0 + q) * L];
+          ar[q] += gv.re * u.re - gv.im * u.im;
+          ai[q] += gv.re * u.im + gv.im * u.re;
+        }
+    }
+  }
+  if (UPDATE && band >= 0) {
+    const int j = info[0], outcome = info[1];
+    const cplx yi = w.yp[(long)b * L + i];
+    const cplx *v = w.v + (long)b * N;
+#pragma unroll
+    for (int q = 0; q < CONT_CPW; ++q)
+      if (q < nk) {
+        const int k = k0 + q;
+        const cplx vk = v[k];
+        // - yp_i conj(v_k)
+        ar[q] -= yi.re * vk.re + yi.im * vk.im;
+        ai[q] -= yi.im * vk.re - yi.re * vk.im;
+        if (k == 0) {
+          if (outcome == 1) {
+            ar[q] = i == j ? 1.0 : 0.0;
+            ai[q] = 0.0;
+          } else if (i == j) {
+            ar[q] = ai[q] = 0.0;
+          }
+        } else if (i == j) {
+          ar[q] = ai[q] = 0.0;
+        }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < CONT_CPW; ++q)
+    if (q < nk) Db[i + (long)(k0 + q) * L] = cplx{ar[q], ai[q]};
+}
+
+// Outcome 0: column 0 (row j already zero) renormalised.
+__global__ __launch_bounds__(256) void cont_norm_kernel(cplx *U, int L, int N, ContWork w) {
+  const int b = blockIdx.x;
+  const int *info = w.info + 4 * b;
+  if (info[2] < 0 || info[1] != 0) return;
+  __shared__ double red[4];
+  cplx *c0 = U + (long)b * L * N;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < L; i += 256) part += c0[i].re * c0[i].re + c0[i].im * c0[i].im;
+  const double n0 = block_sum256(part, red);
+  if (!(n0 > 0.0)) return;
+  const double sc = 1.0 / sqrt(n0);
+  for (int i = threadIdx.x; i < L; i += 256) c0[i] = cplx{c0[i].re * sc, c0[i].im * sc};
+}
+
+__global__ void clock_set_kernel(double *t, int first, int count, double value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) t[first + i] = value;
+}
+
+}  // namespace
+
+int cont_jcap(int Lx, int Ly) {
+  const int Lm = Lx > Ly ? Lx : Ly;
+  return Lm / 2 + (int)std::ceil(std::sqrt(80.0 * Lm + 160.0)) + 64;
+}
+
+hipError_t cont_clock_set(double *t, int first, int count, double value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clock_set_kernel, dim3((count + 255) / 256), dim3(256), 0, s, t, first, count, value);
+  return hipGetLastError();
+}
+
+hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, int Ly, double J,
+                      const double *gamma, double t_end, uint64_t seed, const uint64_t *uid,
+                      const int64_t *step_ptr, int step_offset, const int64_t *step_base,
+                      const ContWork &w, bool *state_in_b, hipStream_t s) {
+  if (L != Lx * (dim == 2 ? Ly : 1) || N < 1 || B < 1 || w.jcap < 1) return hipErrorInvalidValue;
+  if (dim == 1 && Ly != 1) return hipErrorInvalidValue;
+  DrawArgs a{Ua, L, N, dim, Lx, Ly, J, gamma, t_end, seed, uid, step_ptr, step_offset, step_base, w};
+  hipLaunchKernelGGL(cont_draw_kernel, dim3(B), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cont_gemv_kernel, dim3((L + 63) / 64, B), dim3(256), 0, s, (const cplx *)Ua, L, N, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cont_prop_kernel, dim3((L + 255) / 256, B), dim3(256), 0, s, L, Lx, Ly, w);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int nrb = (L + 63) / 64, ncb = (N + 4 * CONT_CPW - 1) / (4 * CONT_CPW);
+  const dim3 grid((unsigned)(nrb * ncb), B);
+  cplx *out;
+  if (dim == 1) {
+    hipLaunchKernelGGL(cont_apply_kernel<true>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0, 2,
+                       nrb, Lx, Ly, w);
+    out = Ub;
+    *state_in_b = true;
+  } else {
+    hipLaunchKernelGGL(cont_apply_kernel<false>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0,
+                       2, nrb, Lx, Ly, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(cont_apply_kernel<true>, grid, dim3(256), 0, s, (const cplx *)Ub, Ua, L, N, Lx, Ly, Lx,
+                       3, nrb, Lx, Ly, w);
+    out = Ua;
+    *state_in_b = false;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(cont_norm_kernel, dim3(B), dim3(256), 0, s, out, L, N, w);
+  return hipGetLastError();
+}
+
+}  // namespace mfq

@@ -116,6 +116,31 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
                       const int64_t *step_base, const PmBlockedWork &w, bool *fallback,
                       hipStream_t s);
 
+// ---------------------------------------------------------------- continuous-time protocol
+// Appendix A, PM protocol with Poisson waiting times: one event per active
+// trajectory (clock t < t_end) per call of cont_event.
+struct ContWork {
+  double *t;      // B: clock of each trajectory
+  cplx *g;        // B x (Lx + Ly): ring rows of P(tau), x row at 0, y row at Lx (1d: Ly = 1)
+  double *jn;     // B x jcap: Bessel-recurrence scratch
+  int *info;      // B x 4: site j, outcome, band x, band y of the last event (band x < 0: none)
+  double *dinfo;  // B x 4: tau, p_j, tau of the reflector, unused
+  cplx *v;        // B x N: reflector vector
+  cplx *y;        // B x L: tau_h U v
+  cplx *yp;       // B x L: P(tau) y
+  int jcap;
+};
+// Scratch length per trajectory for the Bessel recurrence of rings up to max(Lx, Ly).
+int cont_jcap(int Lx, int Ly);
+hipError_t cont_clock_set(double *t, int first, int count, double value, hipStream_t s);
+// One event on every trajectory whose clock is below t_end.  Ua holds the state;
+// the result lands in Ub on the ring (*state_in_b = true) and back in Ua on the
+// torus.  The event index of trajectory b is *step_ptr + step_offset - step_base[b].
+hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, int Ly, double J,
+                      const double *gamma, double t_end, uint64_t seed, const uint64_t *uid,
+                      const int64_t *step_ptr, int step_offset, const int64_t *step_base,
+                      const ContWork &w, bool *state_in_b, hipStream_t s);
+
 // ---------------------------------------------------------------- Cholesky-QR
 struct CholWork {
   cplx *G;       // N x N per trajectory (upper triangle used)

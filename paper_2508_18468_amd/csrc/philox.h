@@ -40,6 +40,6 @@ __device__ __forceinline__ double u01(uint64_t x) {
   return ((double)(x >> 12) + 0.5) * 0x1.0p-52;
 }
 
-enum { PURPOSE_PROJECTIVE = 0, PURPOSE_HOMODYNE = 1 };
+enum { PURPOSE_PROJECTIVE = 0, PURPOSE_HOMODYNE = 1, PURPOSE_CONTINUOUS = 2 };
 
 }  // namespace mfq

@@ -75,6 +75,12 @@ _SIGS = {
     "mfq_occupations": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_pm_events": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_ct_events": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.c_int32]),
+    "mfq_ct_last_events": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_get_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_set_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_get_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mfq_set_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "mfq_synchronize": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -227,6 +233,31 @@ def mfq_pm_events(ctx, n_traj, max_events):
     _check(ctx, lib().mfq_pm_events(ctx, max_events, _ptr(cnt), _ptr(sites), _ptr(outc), _ptr(prob)))
     return [[(int(sites[b, e]), float(prob[b, e]), int(outc[b, e])) for e in range(min(cnt[b], max_events))]
             for b in range(n_traj)]
+
+
+def mfq_ct_events(ctx, gamma, seed, n_events, t_end=float("inf"), reorth_every=0):
+    g = np.ascontiguousarray(gamma, dtype=np.float64)
+    _check(ctx, lib().mfq_ct_events(ctx, _ptr(g), seed, n_events, float(t_end), reorth_every))
+
+
+def mfq_ct_last_events(ctx, n_traj):
+    site = np.zeros(n_traj, dtype=np.int32)
+    outc = np.zeros(n_traj, dtype=np.int32)
+    prob = np.zeros(n_traj)
+    tau = np.zeros(n_traj)
+    _check(ctx, lib().mfq_ct_last_events(ctx, _ptr(site), _ptr(outc), _ptr(prob), _ptr(tau)))
+    return site, outc, prob, tau
+
+
+def mfq_get_times(ctx, n_traj):
+    t = np.zeros(n_traj)
+    _check(ctx, lib().mfq_get_times(ctx, _ptr(t)))
+    return t
+
+
+def mfq_set_times(ctx, t):
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    _check(ctx, lib().mfq_set_times(ctx, _ptr(tt)))
 
 
 def mfq_get_state(ctx, n_traj, L, N):
@@ -436,6 +467,21 @@ class Trajectories:
 
     def pm_events(self, max_events=None):
         return mfq_pm_events(self.ctx, self.n_traj, self.L if max_events is None else max_events)
+
+    def ct_events(self, gamma, seed, n_events, t_end=float("inf"), reorth_every=0):
+        """Continuous-time projective protocol: n_events event slots (mfq_ct_events)."""
+        g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (self.n_traj,))
+        mfq_ct_events(self.ctx, g, seed, n_events, t_end, reorth_every)
+
+    def ct_last_events(self):
+        """(site, outcome, p, tau) per trajectory for the latest event slot (site -1: none)."""
+        return mfq_ct_last_events(self.ctx, self.n_traj)
+
+    def times(self):
+        return mfq_get_times(self.ctx, self.n_traj)
+
+    def set_times(self, t):
+        mfq_set_times(self.ctx, np.broadcast_to(np.asarray(t, dtype=np.float64), (self.n_traj,)))
 
     def get_state(self):
         return mfq_get_state(self.ctx, self.n_traj, self.L, self.N)
