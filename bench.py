@@ -209,6 +209,56 @@ def run_large(args):
     print(json.dumps(out))
 
 
+def run_continuous(args):
+    """Continuous-time projective protocol on the ring1024_pm_ct workload: `steps` event slots
+    (one event per trajectory each) after `warmup`, timed on the host clock around the slots and
+    per kernel with HIP events on the library's stream."""
+    import numpy as np
+    import torch
+    from paper_2508_18468_amd import mfq
+    from paper_2508_18468_amd.workloads import ring_pm_continuous
+    w = ring_pm_continuous()
+    uids = w.uids(0) + w.uids(1) + w.uids(2)
+    B = len(uids)
+    gam = np.repeat(np.asarray(w.gammas), w.n_traj)
+    sim = mfq.Trajectories(1, w.Lx, n_traj=B, uids=uids, device=0)
+    steps, warm = args.steps, args.warmup
+    print(f"{w.name}: L={w.L} N={w.N} trajectories={B}: {warm} warm-up slots, {steps} timed",
+          file=sys.stderr, flush=True)
+    sim.ct_events(gam, w.seed, warm, reorth_every=args.reorth_every)
+    sim.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(50, steps - done)
+        sim.ct_events(gam, w.seed, k, reorth_every=args.reorth_every)
+        sim.synchronize()
+        done += k
+        print(f"  {done}/{steps} slots", file=sys.stderr, flush=True)
+    T = time.perf_counter() - t0
+    phases = sim.phase_times()
+    sim.profile(False)
+    t = sim.times()
+    sim.close()
+    ev_ms = phases["measure"][0] / phases["measure"][1]
+    alg_bytes = 48.0 * w.L * w.N * B  # U read by the GEMV, read and written by the stencil pass
+    achieved = alg_bytes / (ev_ms * 1e-3) / 1e9
+    out = {"metric": "L*N*events/s", "value": B * w.L * w.N * steps / T, "unit": "L*N*events/s",
+           "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": T / steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": w.name, "L": w.L, "N": w.N, "n_traj": B, "gammas": list(w.gammas),
+                      "protocol": "projective, continuous time", "reorth_every": args.reorth_every,
+                      "mean_clock_after": float(np.mean(t))},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                        "kernel": "event slot (draw, GEMV, stencil + rank-1 update)",
+                        "algorithmic_bytes_per_slot": alg_bytes},
+           "phase_ms_per_step": {k: v[0] / steps for k, v in phases.items()}}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,9 +270,11 @@ def main():
                     help="short run for rocprofv3 --pmc passes (3 steps + calibration copy)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
     ap.add_argument("--workload", default="ring1024_qsd",
-                    choices=["ring1024_qsd", "ring16384_pm", "torus160_qsd"],
+                    choices=["ring1024_qsd", "ring16384_pm", "torus160_qsd", "ring1024_pm_ct"],
                     help="ring1024_qsd (default) is the benchmark line; the two large single-"
                          "trajectory shapes time a few steps and their observations")
+    ap.add_argument("--reorth-every", type=int, default=256,
+                    help="ring1024_pm_ct: Cholesky-QR after every this many event slots (0: never)")
     ap.add_argument("--propagator", default="dense", choices=["dense", "factored"],
                     help="large workloads only: dense GEMM (default) or banded / Kronecker form")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_bulk"],
@@ -240,6 +292,9 @@ def main():
               "so the multi-GPU figure is n_gpus x the one-GPU value; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "ring1024_pm_ct":
+        run_continuous(args)
+        return
     if args.workload != "ring1024_qsd":
         run_large(args)
         return

@@ -25,6 +25,7 @@
 // terms beyond order M fall below 1e-20 of the largest and 2 M + 1 <= L, the row
 // is the band |d| <= w (taps below that bound dropped); otherwise the full row
 // comes from its plane-wave sum (1/L) sum_m exp(-i z cos k_m + i k_m d).
+#include <algorithm>
 #include <cmath>
 
 #include "mfq_internal.h"
@@ -314,18 +315,23 @@ __global__ __launch_bounds__(256) void cont_prop_kernel(int L, int Lx, int Ly, C
 // workgroup: lane = row, each wave 4 columns; every load is 64 consecutive rows of
 // one column except where a tap wraps around the ring.
 constexpr int CONT_CPW = 4;
+constexpr int RING_ROWS = 256, RING_CT = 8, RING_WMAX = 32;
+
+// Bands the LDS ring kernel takes (ring direction of a 1d lattice only).
+__device__ __forceinline__ bool ring_lds_band(int band, int L) {
+  return band >= 0 && band <= RING_WMAX && 2 * band + 1 <= L;
+}
+
 template <bool UPDATE>
-__global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D, int L, int N, int stride,
-                                                         int period, int g_off, int band_slot, int nrb,
-                                                         int Lx, int Ly, ContWork w) {
+__device__ __forceinline__ void cont_apply_tile(const cplx *U, cplx *D, int L, int N, int stride, int period,
+                                                int g_off, int band, int rb, int cb, int Lx, int Ly,
+                                                const ContWork &w) {
   const int b = blockIdx.y;
-  const int rb = blockIdx.x % nrb, cb = blockIdx.x / nrb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = rb * 64 + lane;
   const int k0 = cb * (4 * CONT_CPW) + wave * CONT_CPW;
   if (i >= L || k0 >= N) return;
   const int *info = w.info + 4 * b;
-  const int band = info[band_slot];
   const cplx *g = w.g + (long)b * (Lx + Ly) + g_off;
   const Taps t = taps_of(band, period);
   const cplx *Ub = U + (long)b * L * N;
@@ -386,6 +392,93 @@ __global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D,
     if (q < nk) Db[i + (long)(k0 + q) * L] = cplx{ar[q], ai[q]};
 }
 
+// Tiles of 64 rows x 16 columns; the workgroups of a trajectory stride over its ntiles
+// tiles (gridDim.x of them per trajectory).
+template <bool UPDATE>
+__global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D, int L, int N, int stride,
+                                                         int period, int g_off, int band_slot, int nrb,
+                                                         int ntiles, int Lx, int Ly, int skip_lds_bands,
+                                                         ContWork w) {
+  const int b = blockIdx.y;
+  const int *info = w.info + 4 * b;
+  const int band = info[band_slot];
+  if (skip_lds_bands && ring_lds_band(band, L)) return;  // done by cont_ring_kernel
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    cont_apply_tile<UPDATE>(U, D, L, N, stride, period, g_off, band, tile % nrb, tile / nrb, Lx, Ly, w);
+}
+
+// Ring (1d) event pass for bands w <= RING_WMAX: 256 rows x 8 columns per workgroup; the
+// rows r0 - w .. r0 + 255 + w of those columns are staged in LDS by coalesced loads
+// (the halo wraps around the ring), then each thread forms its row of P U for the eight
+// columns from LDS (lanes read consecutive rows: no bank conflicts), subtracts yp v^+
+// and fixes row j / column 0 like cont_apply_kernel<true>.
+__global__ __launch_bounds__(256) void cont_ring_kernel(const cplx *U, cplx *D, int L, int N, int nrb,
+                                                        ContWork w) {
+  const int b = blockIdx.y;
+  const int rb = blockIdx.x % nrb, cb = blockIdx.x / nrb;
+  const int *info = w.info + 4 * b;
+  const int band = info[2];
+  if (!ring_lds_band(band, L)) return;
+  __shared__ cplx s[RING_CT][RING_ROWS + 2 * RING_WMAX];
+  __shared__ cplx gs[2 * RING_WMAX + 1];
+  const int tid = threadIdx.x;
+  const int r0 = rb * RING_ROWS, k0 = cb * RING_CT;
+  const int nk = min(RING_CT, N - k0);
+  const int nrows = RING_ROWS + 2 * band;
+  const cplx *Ub = U + (long)b * L * N + (long)k0 * L;
+  // every load of a thread is issued before the first LDS store (rows tid and 256 + tid)
+  for (int r = tid; r < nrows; r += 256) {
+    int rr = (r0 - band + r) % L;  // rings shorter than the tile wrap more than once
+    if (rr < 0) rr += L;
+    cplx x[RING_CT];
+#pragma unroll
+    for (int c = 0; c < RING_CT; ++c) x[c] = c < nk ? Ub[rr + (long)c * L] : cplx{0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < RING_CT; ++c) s[c][r] = x[c];
+  }
+  const cplx *g = w.g + (long)b * (L + 1);
+  for (int d = tid - band; d <= band; d += 256) gs[d + band] = g[d < 0 ? d + L : d];
+  __syncthreads();
+  const int i = r0 + tid;
+  if (i >= L) return;
+  double ar[RING_CT], ai[RING_CT];
+#pragma unroll
+  for (int c = 0; c < RING_CT; ++c) ar[c] = ai[c] = 0.0;
+  for (int d = -band; d <= band; ++d) {
+    const cplx gv = gs[d + band];
+    const int r = tid + band - d;
+#pragma unroll
+    for (int c = 0; c < RING_CT; ++c) {
+      const cplx u = s[c][r];
+      ar[c] += gv.re * u.re - gv.im * u.im;
+      ai[c] += gv.re * u.im + gv.im * u.re;
+    }
+  }
+  const int j = info[0], outcome = info[1];
+  const cplx yi = w.yp[(long)b * L + i];
+  const cplx *v = w.v + (long)b * N;
+  cplx *Db = D + (long)b * L * N;
+#pragma unroll
+  for (int c = 0; c < RING_CT; ++c) {
+    if (c >= nk) break;
+    const int k = k0 + c;
+    const cplx vk = v[k];
+    double xr = ar[c] - (yi.re * vk.re + yi.im * vk.im);
+    double xi = ai[c] - (yi.im * vk.re - yi.re * vk.im);
+    if (k == 0) {
+      if (outcome == 1) {
+        xr = i == j ? 1.0 : 0.0;
+        xi = 0.0;
+      } else if (i == j) {
+        xr = xi = 0.0;
+      }
+    } else if (i == j) {
+      xr = xi = 0.0;
+    }
+    Db[i + (long)k * L] = cplx{xr, xi};
+  }
+}
+
 // Outcome 0: column 0 (row j already zero) renormalised.
 __global__ __launch_bounds__(256) void cont_norm_kernel(cplx *U, int L, int N, ContWork w) {
   const int b = blockIdx.x;
@@ -433,20 +526,27 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cont_prop_kernel, dim3((L + 255) / 256, B), dim3(256), 0, s, L, Lx, Ly, w);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int nrb = (L + 63) / 64, ncb = (N + 4 * CONT_CPW - 1) / (4 * CONT_CPW);
-  const dim3 grid((unsigned)(nrb * ncb), B);
+  const int nrb = (L + 63) / 64, ncb = (N + 4 * CONT_CPW - 1) / (4 * CONT_CPW), ntiles = nrb * ncb;
   cplx *out;
   if (dim == 1) {
-    hipLaunchKernelGGL(cont_apply_kernel<true>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0, 2,
-                       nrb, Lx, Ly, w);
+    // narrow bands through LDS; wide bands, full rows and trajectories without an event
+    // by the direct pass, whose few workgroups per trajectory exit at once otherwise
+    const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
+    hipLaunchKernelGGL(cont_ring_kernel, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua, Ub,
+                       L, N, rnb, w);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 few((unsigned)std::min(ntiles, 8), B);
+    hipLaunchKernelGGL(cont_apply_kernel<true>, few, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0, 2,
+                       nrb, ntiles, Lx, Ly, 1, w);
     out = Ub;
     *state_in_b = true;
   } else {
+    const dim3 grid((unsigned)ntiles, B);
     hipLaunchKernelGGL(cont_apply_kernel<false>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0,
-                       2, nrb, Lx, Ly, w);
+                       2, nrb, ntiles, Lx, Ly, 0, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cont_apply_kernel<true>, grid, dim3(256), 0, s, (const cplx *)Ub, Ua, L, N, Lx, Ly, Lx,
-                       3, nrb, Lx, Ly, w);
+                       3, nrb, ntiles, Lx, Ly, 0, w);
     out = Ua;
     *state_in_b = false;
   }

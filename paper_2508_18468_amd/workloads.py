@@ -71,6 +71,14 @@ def ring_qsd_batched():
                     0, 100, [interval(0, 512)])
 
 
+def ring_pm_continuous():
+    """1d ring L=1024, N=512, continuous-time projective protocol (Poisson waiting times,
+    total rate gamma N), gamma in {0.1, 0.3, 1.0}, 128 trajectories per gamma, seed 0,
+    run to t = L/2 (the paper's stopping rule); n_steps = event slots timed."""
+    return Workload("ring1024_pm_ct", 1, 1024, 1, PROJECTIVE, (0.1, 0.3, 1.0), 0.0, 200, 128, 0,
+                    0, [interval(0, 512)])
+
+
 def ring_pm_large():
     """1d ring L=16384, N=8192, projective gamma in {0.2, 1.0}, dt=0.05, 4L steps,
     S for l in {L/16, L/8, L/4, L/2}."""

@@ -72,6 +72,7 @@ def _check_state(sim, orc, tol=2e-11):
     (1, 64, 1, [0.3, 1.0, 2.5], 60, 0),      # Bessel band
     (1, 16, 1, [0.05, 0.2, 1.0], 50, 0),     # band wider than the ring: plane-wave row
     (1, 200, 1, [0.7, 4.0], 30, 8),          # ragged row tiles, Cholesky-QR every 8 slots
+    (1, 200, 1, [0.001, 0.7], 12, 0),        # bands wider than the LDS ring kernel takes
     (2, 8, 6, [0.5, 1.5], 40, 0),            # torus, full rows in both directions
     (2, 56, 4, [3.0, 10.0], 40, 5),          # torus, band along x (mostly), full along y
 ])
