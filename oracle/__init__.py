@@ -19,6 +19,7 @@ dynamics of monitored noninteracting fermions on graphics processing units":
 * mutual information                    -- Sec. IV
 * density correlation C(r), G_AB        -- Sec. II Eq. (2), Sec. IV Eq. (5)
 * continuous-time projective protocol   -- Appendix A (Poisson waiting times, one site per event)
+* RK4 homodyne integrator              -- Appendix A (Eq. (A4) integrated by RK4)
 
 Random numbers: Philox4x64-10 (Salmon et al., SC'11), implemented here from
 its published definition, independently of the GPU's implementation.
@@ -38,6 +39,7 @@ from .observables import (correlation_matrix, region_spectrum, entropy_from_spec
                           particle_covariance)
 from .continuous import (event_draws, waiting_time, evolution_operator, evolve, measure_site,
                          state_from_correlation, run_continuous)
+from .rk4 import generator as rk4_generator, rk4_propagate, rk4_step, run_rk4
 
 __all__ = [
     "Lattice", "hopping_matrix", "default_occupied", "propagator",
@@ -48,4 +50,5 @@ __all__ = [
     "entanglement_entropy", "mutual_information", "density_correlation", "particle_covariance",
     "event_draws", "waiting_time", "evolution_operator", "evolve", "measure_site",
     "state_from_correlation", "run_continuous",
+    "rk4_generator", "rk4_propagate", "rk4_step", "run_rk4",
 ]
