@@ -234,6 +234,22 @@ mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double d
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out);
 
+/* Integrator of homodyne steps (mfq_step, mfq_run, Appendix A, Eq. (A4)).
+ * MFQ_INTEGRATOR_SPLIT (default): U <- P U with the exact propagator P = exp(-i Ht dt), then
+ *   each row scaled by exp(dW_i + (2 p_i - 1) gamma dt) with p of the propagated U.
+ * MFQ_INTEGRATOR_RK4: the paper's fourth-order Runge-Kutta step of Eq. (A4) with its exponent
+ *   A = -i Ht dt + diag(dW + (2 p - 1) gamma dt) frozen over the step (p of the state entering
+ *   the step, the same normals dW_i = sqrt(gamma dt) z_i): U <- U + (k1 + 2 k2 + 2 k3 + k4)/6,
+ *   evaluated as the degree-4 Taylor polynomial of exp(A) in Horner form, four nearest-
+ *   neighbour passes over U and no L x L propagator.  Needs a third state buffer
+ *   (16 L N n_traj bytes), allocated by the first RK4 step.  The fused path integrates by
+ *   split step only, so mfq_run takes the per-phase kernels under RK4.
+ * Projective steps are unaffected.  Errors: MFQ_EINVAL (unknown integrator); the first RK4
+ * step may return MFQ_ENOMEM. */
+#define MFQ_INTEGRATOR_SPLIT 0
+#define MFQ_INTEGRATOR_RK4 1
+mfq_status mfq_set_integrator(mfq_ctx *ctx, int32_t integrator);
+
 /* Form in which exp(-i Ht dt) is applied (Appendix A free evolution).
  *   MFQ_PROP_DENSE     the dense L x L propagator as one GEMM over the batch (default; FP32
  *                      planes with MFQ_FP32_BULK);

@@ -50,6 +50,10 @@ struct mfq_ctx {
   PmBlockedWork pmb{};
   int pm_path = 0;  // MFQ_PM_AUTO
   ContWork ct{};    // continuous-time protocol: clocks, ring rows, event records
+  int integrator = 0;       // MFQ_INTEGRATOR_SPLIT
+  int g_integ = -1;         // integrator the cached graph was captured with
+  void *rk_buf = nullptr;   // RK4 scratch (a third state buffer and the diagonal), on first use
+  size_t rk_cap = 0;
   bool ct_any = false;  // an event batch has run since mfq_init_state
   std::vector<double> gamma_host;
   // phase timing
@@ -381,6 +385,29 @@ bool blocked_pm(const mfq_ctx *c) {
   return c->pm_path == MFQ_PM_AUTO && c->L >= PM_BLOCKED_MIN_L;
 }
 
+size_t rk4_state_bytes(const mfq_ctx *c) {
+  return align_up((size_t)c->L * c->N * c->B * sizeof(cplx));
+}
+
+// RK4 scratch: a third state buffer and the diagonal (L per trajectory), allocated on first
+// use outside any graph capture.
+mfq_status ensure_rk4(mfq_ctx *c) {
+  const size_t need = rk4_state_bytes(c) + (size_t)c->L * c->B * sizeof(double);
+  if (c->rk_cap >= need) return MFQ_OK;
+  if (c->rk_buf) {
+    HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+    (void)hipFree(c->rk_buf);
+    c->rk_buf = nullptr;
+    c->rk_cap = 0;
+  }
+  if (hipMalloc(&c->rk_buf, need) != hipSuccess) {
+    c->rk_buf = nullptr;
+    return fail(c, MFQ_ENOMEM, "hipMalloc of the RK4 scratch failed");
+  }
+  c->rk_cap = need;
+  return MFQ_OK;
+}
+
 bool factored_propagator(const mfq_ctx *c) {
   return c->prop_form == MFQ_PROP_FACTORED && (c->lat.dim == 2 || c->band_w >= 0);
 }
@@ -393,7 +420,18 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
   const int L = c->L, N = c->N, B = c->B;
   cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
   int pidx = 1 - c->cur;
-  {
+  const bool rk4 = protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4;
+  if (rk4) {  // homodyne step by RK4: the whole step in place on the current buffer
+    PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
+    const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+    cplx *V2 = reinterpret_cast<cplx *>(c->rk_buf);
+    double *a = reinterpret_cast<double *>(reinterpret_cast<char *>(c->rk_buf) + rk4_state_bytes(c));
+    HIPCHK(born_only(Xa, c->p, L, N, B, c->stream), "born");
+    HIPCHK(rk4_homodyne(Xa, Xb, V2, c->p, a, L, N, B, c->lat.dim, c->lat.Lx, Ly, c->lat.J, c->gamma, dt, seed,
+                        c->uid, c->step_dev, step_offset, c->step_base, c->stream), "rk4 homodyne");
+    pidx = c->cur;
+  }
+  if (!rk4) {
     PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
     if (factored_propagator(c) && c->lat.dim == 1) {
       HIPCHK(ring_stencil(Xa, Xb, c->gx, L, c->band_w, (long)N * B, c->stream), "propagator band");
@@ -429,7 +467,7 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
   }
   Xb = c->X[pidx];          // propagated state
   Xa = c->X[1 - pidx];      // free buffer
-  {
+  if (!rk4) {
     PhaseTimer t(c, MFQ_PHASE_MEASURE);
     if (protocol == MFQ_HOMODYNE) {
       HIPCHK(born_homodyne(Xb, c->p, L, N, B, c->gamma, dt, seed, c->uid, c->step_dev, step_offset,
@@ -473,7 +511,7 @@ void drop_graph(mfq_ctx *c) {
 // parity change.  Replayed with hipGraphLaunch for each pair of steps.
 mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed) {
   if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur &&
-      c->g_tile == c->tile_mode && c->g_prop == c->prop_form)
+      c->g_tile == c->tile_mode && c->g_prop == c->prop_form && c->g_integ == c->integrator)
     return MFQ_OK;
   drop_graph(c);
   const int cur0 = c->cur;
@@ -498,6 +536,7 @@ mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed)
   c->g_cur = cur0;
   c->g_tile = c->tile_mode;
   c->g_prop = c->prop_form;
+  c->g_integ = c->integrator;
   return MFQ_OK;
 }
 
@@ -538,6 +577,7 @@ mfq_status mfq_destroy(mfq_ctx *c) {
   drop_graph(c);
   if (c->run_S) (void)hipFree(c->run_S);
   if (c->red_buf) (void)hipFree(c->red_buf);
+  if (c->rk_buf) (void)hipFree(c->rk_buf);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -645,6 +685,7 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
   if (n_steps == 0) return MFQ_OK;
   mfq_status st0 = prepare_step(c, gamma, dt);
   if (st0) return st0;
+  if (protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4 && (st0 = ensure_rk4(c))) return st0;
   HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
   int done = 0;
   const bool capturable = !(protocol == MFQ_PROJECTIVE && blocked_pm(c));
@@ -754,6 +795,15 @@ mfq_status mfq_set_times(mfq_ctx *c, const double *t_host) {
   return MFQ_OK;
 }
 
+mfq_status mfq_set_integrator(mfq_ctx *c, int32_t integrator) {
+  if (!c) return MFQ_EINVAL;
+  if (integrator != MFQ_INTEGRATOR_SPLIT && integrator != MFQ_INTEGRATOR_RK4)
+    return fail(c, MFQ_EINVAL, "unknown integrator");
+  c->integrator = integrator;
+  drop_graph(c);
+  return MFQ_OK;
+}
+
 mfq_status mfq_set_propagator(mfq_ctx *c, int32_t form) {
   if (!c) return MFQ_EINVAL;
   if (form != MFQ_PROP_DENSE && form != MFQ_PROP_FACTORED)
@@ -804,7 +854,8 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   if (n_obs_out) *n_obs_out = n_obs;
   if (n_steps == 0) return MFQ_OK;
   const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
-  const bool fits = fused_fits(c->L, c->N, c->lat.Lx, Ly);
+  const bool fits = fused_fits(c->L, c->N, c->lat.Lx, Ly) &&
+                    !(protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4);
   if (c->run_path == MFQ_PATH_FUSED && !fits)
     return fail(c, MFQ_EINVAL, "problem does not fit the fused path (LDS)");
   const bool fused = c->run_path == MFQ_PATH_FUSED || (c->run_path == MFQ_PATH_AUTO && fits);
@@ -997,7 +1048,8 @@ mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, doubl
                              {MFQ_PATH_LAUNCHES, MFQ_TILE_SMALL},
                              {MFQ_PATH_LAUNCHES, MFQ_TILE_LARGE}};
   const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
-  if (fused_fits(c->L, c->N, c->lat.Lx, Ly)) cands.push_back({MFQ_PATH_FUSED, MFQ_TILE_AUTO});
+  if (fused_fits(c->L, c->N, c->lat.Lx, Ly) && !(protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4))
+    cands.push_back({MFQ_PATH_FUSED, MFQ_TILE_AUTO});
   std::memset(out, 0, sizeof(*out));
   int best = -1;
   double best_ms = 0.0;

@@ -141,6 +141,16 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
                       const int64_t *step_ptr, int step_offset, const int64_t *step_base,
                       const ContWork &w, bool *state_in_b, hipStream_t s);
 
+// ---------------------------------------------------------------- RK4 homodyne step
+// Appendix A: the homodyne step with Eq. (A4)'s exponent frozen over the step and
+// integrated by RK4 (the degree-4 Taylor polynomial of exp(A), in Horner form).
+// U (L x N per trajectory) is updated in place; p holds the Born probabilities of U;
+// V1, V2 (L x N per trajectory) and a (L per trajectory) are scratch.
+hipError_t rk4_homodyne(cplx *U, cplx *V1, cplx *V2, const double *p, double *a, int L, int N, int B, int dim,
+                        int Lx, int Ly, double J, const double *gamma, double dt, uint64_t seed,
+                        const uint64_t *uid, const int64_t *step_ptr, int step_offset,
+                        const int64_t *step_base, hipStream_t s);
+
 // ---------------------------------------------------------------- Cholesky-QR
 struct CholWork {
   cplx *G;       // N x N per trajectory (upper triangle used)

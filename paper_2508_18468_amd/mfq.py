@@ -96,6 +96,7 @@ _SIGS = {
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_propagator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_set_integrator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_propagator_band": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_particle_covariance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -317,6 +318,7 @@ def mfq_set_tuning(ctx, path, tile):
 
 
 PROP_DENSE, PROP_FACTORED = 0, 1
+INTEGRATOR_SPLIT, INTEGRATOR_RK4 = 0, 1
 
 
 def mfq_set_propagator(ctx, form):
@@ -514,6 +516,10 @@ class Trajectories:
 
     def set_propagator(self, form):
         mfq_set_propagator(self.ctx, form)
+
+    def set_integrator(self, integrator):
+        """INTEGRATOR_SPLIT (default) or INTEGRATOR_RK4 for homodyne steps."""
+        _check(self.ctx, lib().mfq_set_integrator(self.ctx, integrator))
 
     def propagator_band(self):
         return mfq_propagator_band(self.ctx)
