@@ -177,27 +177,42 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
       if ((e = zgemm(g, s)) != hipSuccess) return e;
     }
   }
-  // R^{-1}: block column J = -(R^{-1})_{0:J,0:J} R_{0:J,J} (R_JJ)^{-1}
-  for (int J = 1; J < nJ; ++J) {
-    const int c0 = J * NB, w = std::min(NB, N - c0);
-    {
-      GemmDesc g = desc();
-      g.skip_if_le = skip; g.skip_thr = thr;
-      g.M = c0; g.N = w; g.K = c0; g.batch = B;
-      g.A = wk.Rinv; g.lda = N; g.sA = NN; g.opA = OP_N; g.aUpper = 1;
-      g.B = wk.G + (long)c0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
-      g.D = wk.T; g.ldd = N; g.sD = (long)N * NB;
-      if ((e = zgemm(g, s)) != hipSuccess) return e;
-    }
-    {
-      GemmDesc g = desc();
-      g.skip_if_le = skip; g.skip_thr = thr;
-      g.M = c0; g.N = w; g.K = w; g.batch = B;
-      g.A = wk.T; g.lda = N; g.sA = (long)N * NB; g.opA = OP_N;
-      g.B = wk.Rinv + c0 + (long)c0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;
-      g.D = wk.Rinv + (long)c0 * N; g.ldd = N; g.sD = NN;
-      g.alpha = cplx{-1.0, 0.0};
-      if ((e = zgemm(g, s)) != hipSuccess) return e;
+  // R^{-1} from the inverted diagonal blocks, level by level: adjacent aligned diagonal
+  // blocks [R11 R12; 0 R22] of size S (S = NB, 2 NB, ...) have the inverse
+  // [R11^{-1}, -R11^{-1} R12 R22^{-1}; 0, R22^{-1}], so one level is two batched products
+  // over all its block pairs and all trajectories (T = R11^{-1} R12, then -T R22^{-1}); the
+  // last pair of a level may have a narrower right block.  T lives in Uout, which is free
+  // until the final product (at most N^2 / 2 <= L N entries per trajectory).
+  for (long S = NB; S < N; S *= 2) {
+    const int full = (int)(N / (2 * S));                        // pairs with a complete right block
+    const int w2 = (int)(N - (long)full * 2 * S - S);           // right width of a last, narrower pair
+    for (int part = 0; part < 2; ++part) {
+      const int npairs = part == 0 ? full : (w2 > 0 ? 1 : 0);
+      if (npairs == 0) continue;
+      const long r0 = part == 0 ? 0 : (long)full * 2 * S;       // first pair's left block
+      const int wR = part == 0 ? (int)S : w2;                   // right block width
+      cplx *T = Uout + (part == 0 ? 0 : (long)full * S * S);
+      const long step = 2 * S * ((long)N + 1);                  // between pairs along the diagonal
+      {  // T = R11^{-1} R12
+        GemmDesc g = desc();
+        g.skip_if_le = skip; g.skip_thr = thr;
+        g.M = (int)S; g.N = wR; g.K = (int)S; g.batch = B * npairs; g.batch2 = npairs;
+        g.A = wk.Rinv + r0 * ((long)N + 1); g.lda = N; g.sA = NN; g.sA2 = step; g.opA = OP_N; g.aUpper = 1;
+        g.B = wk.G + r0 + (r0 + S) * N; g.ldb = N; g.sB = NN; g.sB2 = step; g.opB = OP_N;
+        g.D = T; g.ldd = S; g.sD = (long)L * N; g.sD2 = S * S;
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
+      {  // (R^{-1})_12 = -T R22^{-1}
+        GemmDesc g = desc();
+        g.skip_if_le = skip; g.skip_thr = thr;
+        g.M = (int)S; g.N = wR; g.K = wR; g.batch = B * npairs; g.batch2 = npairs;
+        g.A = T; g.lda = S; g.sA = (long)L * N; g.sA2 = S * S; g.opA = OP_N;
+        g.B = wk.Rinv + (r0 + S) * ((long)N + 1); g.ldb = N; g.sB = NN; g.sB2 = step; g.opB = OP_N;
+        g.bUpper = 1;
+        g.D = wk.Rinv + r0 + (r0 + S) * N; g.ldd = N; g.sD = NN; g.sD2 = step;
+        g.alpha = cplx{-1.0, 0.0};
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
     }
   }
   // Uout = Uin R^{-1}; in the second pass a copy when Uin is already orthonormal to

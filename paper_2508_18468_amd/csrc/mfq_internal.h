@@ -45,6 +45,10 @@ struct GemmDesc {
   // square B, bUpper): if *copy_if_le <= copy_thr, D = A is copied instead.
   const double *copy_if_le;
   double copy_thr;
+  // Two batch dimensions: with batch2 > 1, entry b of the batch is (b / batch2, b % batch2)
+  // and its operands sit at X + (b / batch2) sX + (b % batch2) sX2 (batch2 <= 1: X + b sX).
+  int batch2;
+  long sA2, sB2, sD2, sCin2;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);

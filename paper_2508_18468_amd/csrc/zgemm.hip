@@ -161,6 +161,12 @@ __device__ __forceinline__ void reduce_epilogue(const GemmDesc &g, const d4 (&ac
 // GATHER: storage rows of A / B are looked up through idxA / idxB.
 // EDGE: bounds-checked loads and stores (M, N or K not multiples of the tile).
 
+// Offset of batch entry b for the strides (s, s2) of one operand.
+__device__ __forceinline__ long batch_offset(const GemmDesc &g, int b, long s, long s2) {
+  if (g.batch2 <= 1) return (long)b * s;
+  return (long)(b / g.batch2) * s + (long)(b % g.batch2) * s2;
+}
+
 template <int OPA, int OPB, int MT, int NT, int KT, bool GATHER, bool EDGE, int FL = 0>
 __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   // waves: 2 along M; NT/32 along N (2 for 64x64 tiles, 4 for 128x128 tiles)
@@ -191,8 +197,8 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   if (g.tri == TRI_UPPER && m0 > n0 + NT - 1) return;  // tile entirely below the diagonal
   if constexpr ((FL & FL_COPYSKIP) != 0) {
     if (*g.copy_if_le <= g.copy_thr) {  // the factor is the identity to the accuracy kept
-      const cplx *Ab = g.A + (long)b * g.sA;
-      cplx *Db = g.D + (long)b * g.sD;
+      const cplx *Ab = g.A + batch_offset(g, b, g.sA, g.sA2);
+      cplx *Db = g.D + batch_offset(g, b, g.sD, g.sD2);
       for (int e = threadIdx.x; e < MT * NT; e += blockDim.x) {
         const int row = m0 + e % MT, col = n0 + e / MT;
         if (row < g.M && col < g.N) Db[row + (long)col * g.ldd] = Ab[row + (long)col * g.lda];
@@ -209,8 +215,8 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WM, wc = wave / WM;
-  const cplx *A = g.A + (long)b * g.sA;
-  const cplx *B = g.B + (long)b * g.sB;
+  const cplx *A = g.A + batch_offset(g, b, g.sA, g.sA2);
+  const cplx *B = g.B + batch_offset(g, b, g.sB, g.sB2);
   const int *idxA = GATHER && g.idxA ? g.idxA + (long)b * g.sIdxA : nullptr;
   const int *idxB = GATHER && g.idxB ? g.idxB + (long)b * g.sIdxB : nullptr;
 
@@ -346,9 +352,9 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   }
   // epilogue: D = alpha * acc + beta * Cin
   const bool useC = (g.beta.re != 0.0 || g.beta.im != 0.0);
-  const cplx *Cin = g.Cin ? g.Cin + (long)b * g.sCin : nullptr;
-  cplx *D = g.D + (long)b * g.sD;
-  cplx *R1 = (FL & FL_NEAR_ID) ? g.R1 + (long)b * g.sD : nullptr;
+  const cplx *Cin = g.Cin ? g.Cin + batch_offset(g, b, g.sCin, g.sCin2) : nullptr;
+  cplx *D = g.D + batch_offset(g, b, g.sD, g.sD2);
+  cplx *R1 = (FL & FL_NEAR_ID) ? g.R1 + batch_offset(g, b, g.sD, g.sD2) : nullptr;
   double dmax = 0.0;
   const double qnan = __longlong_as_double(0x7ff8000000000000ll);
 #pragma unroll
