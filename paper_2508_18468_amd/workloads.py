@@ -88,6 +88,16 @@ def ring_pm_large():
                              interval(0, L // 2)])
 
 
+def ring_qsd_large():
+    """1d ring L=16384, N=8192, homodyne gamma in {0.2, 1.0} (one trajectory each), dt=0.05,
+    run to t = L (327680 steps; the shape of the paper's longest homodyne timing), S for
+    l in {L/16, L/8, L/4, L/2}."""
+    L = 16384
+    return Workload("ring16384_qsd", 1, L, 1, HOMODYNE, (0.2, 1.0), 0.05, 20 * L, 1, 0,
+                    L // 8, [interval(0, L // 16), interval(0, L // 8), interval(0, L // 4),
+                             interval(0, L // 2)])
+
+
 def torus_qsd():
     """2d 160x160 torus, homodyne gamma in {0.5, 1.0, 2.0}, dt=0.05; mutual information
     of the strips x in [0,40) and x in [80,120) (all y)."""
