@@ -1,5 +1,5 @@
-"""Ensemble pins: exact mean map of the projective protocol and the dephasing limit
-of the homodyne protocol, plus planted mistakes that these pins must catch."""
+"""Ensemble pins: exact mean maps of the projective protocol (discrete and continuous time) and
+the dephasing limit of the homodyne protocol, plus planted mistakes that these pins must catch."""
 
 import numpy as np
 import pytest
@@ -57,6 +57,45 @@ def lindblad(lat, gamma, t):
     C0 = correlation_matrix(initial_state(L, default_occupied(lat)))
     v = linalg.expm(G * t) @ C0.ravel(order="F")
     return v.reshape((L, L), order="F")
+
+
+def ct_mean_map(lat, gamma, N, n_events):
+    """Mean of C after n events of the continuous-time projective protocol.  Averaging one event
+    over the waiting time tau ~ gamma N exp(-gamma N tau) maps the energy-basis entries X_ab of C
+    to K_ab X_ab with K_ab = G / (G + i (e_a - e_b)), G = gamma N (the Laplace transform of
+    exp(-i (e_a - e_b) tau)); averaging over the uniform site j and its Born outcome removes row
+    and column j off the diagonal (the outcome-weighted mean of Eq. (A1) and Eq. (A2)), i.e.
+    multiplies every off-diagonal entry by 1 - 2/L.  Both maps are linear, so
+    E[C_n] = (M o R)^n (C_0)."""
+    H = hopping_matrix(lat)
+    eps, V = np.linalg.eigh(H)
+    G = gamma * N
+    K = G / (G + 1j * (eps[:, None] - eps[None, :]))
+    L = lat.L
+    M = np.full((L, L), 1.0 - 2.0 / L)
+    np.fill_diagonal(M, 1.0)
+    C = correlation_matrix(initial_state(L, default_occupied(lat)))
+    for _ in range(n_events):
+        C = M * (V @ (K * (V.T @ C @ V)) @ V.T)
+    return C
+
+
+def _ct_ensemble(lat, gamma, n_events, n_traj, seed=3):
+    from oracle.continuous import run_continuous
+    U0 = initial_state(lat.L, default_occupied(lat))
+    Cs = np.array([correlation_matrix(run_continuous(lat, U0, gamma, seed, uid, n_events)["U"])
+                   for uid in range(n_traj)])
+    se = (Cs.real.std(axis=0, ddof=1) + 1j * Cs.imag.std(axis=0, ddof=1)) / np.sqrt(n_traj)
+    return Cs.mean(axis=0), se
+
+
+@pytest.mark.slow
+def test_continuous_time_mean_map():
+    lat = Lattice(1, 6)
+    mean, se = _ct_ensemble(lat, 1.0, 4, 3000)
+    assert _z(mean, se, ct_mean_map(lat, 1.0, 3, 4)) < 4.5
+    # a total rate gamma L instead of gamma N (the other reading of the rate) is a different law
+    assert _z(mean, se, ct_mean_map(lat, 2.0, 3, 4)) > 6
 
 
 @pytest.mark.slow
