@@ -70,8 +70,18 @@ def cpu_baseline(w, steps):
                 n_ts += 1
             oracle.entanglement_entropy(U, w.regions[0])
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return {"value": n_ts * w.L * w.N / dt, "unit": "L*N*steps/s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "cpus_available": affinity,
             "sample": f"2 trajectories x {steps} steps per gamma ({n_ts} trajectory-steps) of the same "
                       f"L={w.L} homodyne workload plus one entropy each, numpy/LAPACK FP64; "
                       f"{dt:.1f} s wall"}
