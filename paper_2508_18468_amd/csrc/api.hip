@@ -877,7 +877,6 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   const size_t need = (size_t)std::max(n_obs, 1) * c->B;
   if (need > c->run_S_cap) {
     if (c->run_S) (void)hipFree(c->run_S);
-  if (c->red_buf) (void)hipFree(c->red_buf);
     c->run_S = nullptr;
     c->run_S_cap = 0;
     HIPCHK(hipMalloc(&c->run_S, need * sizeof(double)), "observation buffer");

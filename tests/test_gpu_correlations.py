@@ -95,3 +95,26 @@ def test_long_ring_identities_full_size():
         want = float((lam[t] * (1.0 - lam[t])).sum())
         assert abs(G[t] - want) <= 1e-9 * want, (t, G[t], want)
     sim.close()
+
+
+def test_correlation_buffer_survives_fused_runs():
+    """Regression: growing the fused path's observation buffer must leave the correlation
+    buffer of the same context alone.  C(r) before and after fused runs with observations,
+    against the oracle on the same trajectories."""
+    from paper_2508_18468_amd import mfq
+    L, dt, seed, uids, gams = 64, 0.05, 5, [1, 2], [0.5, 1.5]
+    sim = make_sim(1, L, n_traj=2, uids=uids)
+    ob = OracleBatch(1, L, 1, dt, uids)
+    sim.density_correlation()                    # allocates the correlation buffer
+    sim.set_path(mfq.PATH_FUSED)
+    region = list(range(L // 2))
+    for n_steps, every in ((4, 2), (12, 1)):     # the second run needs a larger buffer
+        sim.run(QSD, gams, dt, seed, n_steps, obs_every=every, region=region)
+        for _ in range(n_steps):
+            ob.step(QSD, gams, seed)
+    Cr = sim.density_correlation()
+    G = sim.particle_covariance(list(range(8)), list(range(32, 40)))
+    for t in range(2):
+        assert np.abs(Cr[t] - oracle.density_correlation(ob.U[t])).max() <= 1e-12
+        assert abs(G[t] - oracle.particle_covariance(ob.U[t], list(range(8)), list(range(32, 40)))) <= 1e-12
+    sim.close()
