@@ -234,6 +234,32 @@ mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double d
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out);
 
+/* Several contexts in ONE launch of the fused kernel (execution form: trajectories of
+ * uneven lattices, protocols and monitoring rates batched into one persistent launch).
+ * ctx[k] runs args[k].n_steps steps of its own protocol, gamma (n_traj host doubles), dt and
+ * seed, with S of its own region observed after every step whose absolute index is a
+ * multiple of obs_every (0: none) into args[k].S_host (n_obs x n_traj doubles, observation-
+ * major; args[k].n_obs is set on return).  Each workgroup finds its context in a table and
+ * runs one trajectory with its state in LDS, exactly as mfq_run on the fused path does
+ * (same random numbers, same results).  1 <= n <= 8 distinct contexts on one device, each of
+ * which must fit the fused path (split-step integrator).  The launch is enqueued on ctx[0]'s
+ * stream after the work already queued on the others' streams; the call synchronises.
+ * Errors: MFQ_EINVAL (as mfq_run, too many or repeated contexts, different devices),
+ * MFQ_ESTATE, MFQ_ENUMERIC (per context, the first one reported), MFQ_EDEVICE. */
+typedef struct {
+  int32_t protocol;
+  const double *gamma;
+  double dt;
+  uint64_t seed;
+  int32_t n_steps;
+  int32_t obs_every;
+  const int32_t *region;
+  int32_t n_sites;
+  double *S_host;
+  int32_t n_obs; /* out */
+} mfq_run_args;
+mfq_status mfq_run_group(mfq_ctx *const *ctx, mfq_run_args *args, int32_t n);
+
 /* Integrator of homodyne steps (mfq_step, mfq_run, Appendix A, Eq. (A4)).
  * MFQ_INTEGRATOR_SPLIT (default): U <- P U with the exact propagator P = exp(-i Ht dt), then
  *   each row scaled by exp(dW_i + (2 p_i - 1) gamma dt) with p of the propagated U.

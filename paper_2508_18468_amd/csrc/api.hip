@@ -804,6 +804,107 @@ mfq_status mfq_set_integrator(mfq_ctx *c, int32_t integrator) {
   return MFQ_OK;
 }
 
+mfq_status mfq_run_group(mfq_ctx *const *ctxs, mfq_run_args *args, int32_t n) {
+  if (!ctxs || !args || n < 1) return MFQ_EINVAL;
+  if (n > FUSED_GROUP_MAX) return fail(ctxs[0], MFQ_EINVAL, "too many contexts for one launch");
+  for (int k = 0; k < n; ++k) {
+    mfq_ctx *c = ctxs[k];
+    if (!c) return MFQ_EINVAL;
+    for (int q = 0; q < k; ++q)
+      if (ctxs[q] == c) return fail(c, MFQ_EINVAL, "a context appears twice");
+    if (c->device != ctxs[0]->device) return fail(c, MFQ_EINVAL, "contexts on different devices");
+    const mfq_run_args &r = args[k];
+    mfq_status st = validate_step(c, r.protocol, r.gamma, r.dt, r.n_steps);
+    if (st) return st;
+    if (r.obs_every < 0) return fail(c, MFQ_EINVAL, "obs_every < 0");
+    if (r.obs_every > 0 && (st = validate_region(c, r.region, r.n_sites))) return st;
+    const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+    if (!fused_fits(c->L, c->N, c->lat.Lx, Ly))
+      return fail(c, MFQ_EINVAL, "problem does not fit the fused path (LDS)");
+    if (r.protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4)
+      return fail(c, MFQ_EINVAL, "the fused path integrates by split step only");
+    const int n_obs = r.obs_every > 0 ? (int)((c->step + r.n_steps) / r.obs_every - c->step / r.obs_every) : 0;
+    if (n_obs > 0 && !r.S_host) return fail(c, MFQ_EINVAL, "S_host is NULL");
+    args[k].n_obs = n_obs;
+  }
+  mfq_ctx *c0 = ctxs[0];
+  FusedGroup grp{};
+  grp.n = n;
+  grp.first[0] = 0;
+  for (int k = 0; k < n; ++k) {
+    mfq_ctx *c = ctxs[k];
+    const mfq_run_args &r = args[k];
+    mfq_status st = prepare_step(c, r.gamma, r.dt);
+    if (st) return st;
+    const size_t need = (size_t)std::max(r.n_obs, 1) * c->B;
+    if (need > c->run_S_cap) {
+      HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+      if (c->run_S) (void)hipFree(c->run_S);
+      c->run_S = nullptr;
+      c->run_S_cap = 0;
+      HIPCHK(hipMalloc(&c->run_S, need * sizeof(double)), "observation buffer");
+      c->run_S_cap = need;
+    }
+    if (r.obs_every > 0 && r.n_sites > 0)
+      HIPCHK(hipMemcpyAsync(c->region, r.region, r.n_sites * sizeof(int), hipMemcpyHostToDevice, c->stream),
+             "region upload");
+    FusedArgs &a = grp.g[k];
+    a.P = c->P; a.U = c->X[c->cur]; a.L = c->L; a.N = c->N;
+    a.gx = c->gx; a.gy = c->gy; a.Lx = c->lat.Lx; a.Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+    a.gamma = c->gamma; a.dt = r.dt; a.seed = r.seed; a.uid = c->uid; a.step_base = c->step_base;
+    a.step0 = c->step; a.n_steps = r.n_steps; a.protocol = r.protocol;
+    a.obs_every = r.obs_every; a.region = c->region; a.nreg = r.obs_every > 0 ? r.n_sites : 0;
+    a.max_obs = r.n_obs; a.S_out = c->run_S;
+    a.ev_sites = c->pm_sites; a.ev_out = c->pm_out; a.ev_cnt = c->pm_cnt; a.ev_prob = c->pm_prob;
+    a.flag = c->flag;
+    a.B = c->B;
+    grp.first[k + 1] = grp.first[k] + c->B;
+  }
+  // the launch goes on the first context's stream, ordered after the work already queued on
+  // the others' streams, and theirs after it
+  std::vector<hipEvent_t> evs;
+  auto cleanup = [&]() {
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+  };
+  for (int k = 1; k < n; ++k) {
+    if (ctxs[k]->stream == c0->stream) continue;
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(c0, MFQ_EDEVICE, "event create");
+    }
+    evs.push_back(ev);
+    if (hipEventRecord(ev, ctxs[k]->stream) != hipSuccess || hipStreamWaitEvent(c0->stream, ev, 0) != hipSuccess) {
+      cleanup();
+      return fail(c0, MFQ_EDEVICE, "stream ordering");
+    }
+  }
+  hipError_t le = fused_run_group(grp, c0->stream);
+  if (le != hipSuccess) {
+    cleanup();
+    return hip_fail(c0, le, "fused group kernel");
+  }
+  for (int k = 0; k < n; ++k) {
+    mfq_ctx *c = ctxs[k];
+    if (args[k].n_obs > 0 &&
+        hipMemcpyAsync(args[k].S_host, c->run_S, (size_t)args[k].n_obs * c->B * sizeof(double),
+                       hipMemcpyDeviceToHost, c0->stream) != hipSuccess) {
+      cleanup();
+      return fail(c, MFQ_EDEVICE, "observation download");
+    }
+  }
+  const hipError_t se = hipStreamSynchronize(c0->stream);
+  cleanup();
+  if (se != hipSuccess) return hip_fail(c0, se, "synchronize");
+  mfq_status worst = MFQ_OK;
+  for (int k = 0; k < n; ++k) {
+    ctxs[k]->step += args[k].n_steps;
+    const mfq_status st = check_flag(ctxs[k]);
+    if (st && !worst) worst = st;
+  }
+  return worst;
+}
+
 mfq_status mfq_set_propagator(mfq_ctx *c, int32_t form) {
   if (!c) return MFQ_EINVAL;
   if (form != MFQ_PROP_DENSE && form != MFQ_PROP_FACTORED)
@@ -894,6 +995,7 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   a.max_obs = n_obs; a.S_out = c->run_S;
   a.ev_sites = c->pm_sites; a.ev_out = c->pm_out; a.ev_cnt = c->pm_cnt; a.ev_prob = c->pm_prob;
   a.flag = c->flag;
+  a.B = c->B;
   {
     PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
     HIPCHK(fused_run(a, c->B, c->stream), "fused trajectory kernel");

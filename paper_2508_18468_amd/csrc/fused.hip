@@ -16,6 +16,8 @@
 //   Householder tridiagonalisation, bisection, entropy sum; Sec. II).
 // Random numbers are the same Philox draws as the per-phase kernels, so the
 // two paths compute the same trajectory up to rounding.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace mfq {
@@ -135,8 +137,8 @@ __device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// All steps and observations of trajectory b of the context described by a, in LDS.
+__device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned char *smem) {
   const FusedLayout f = fused_layout(a.L, a.N, a.Lx, a.Ly);
   cplx *Ua = reinterpret_cast<cplx *>(smem + f.ua);
   cplx *Ub = reinterpret_cast<cplx *>(smem + f.ub);
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {
   __shared__ double red[4];
   __shared__ int bad;
 
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int L = a.L, N = a.N, lu = L + 1, lg = N + 1;
   cplx *Ug = a.U + (long)b * L * N;
   const double g = a.gamma[b];
@@ -274,7 +276,7 @@ __global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {
         for (int k = tid; k < m; k += 256) part += binary_entropy(lam[k]);
         S = block_sum256(part, red);
       }
-      if (tid == 0 && n_obs < a.max_obs) a.S_out[(long)n_obs * gridDim.x + b] = S;
+      if (tid == 0 && n_obs < a.max_obs) a.S_out[(long)n_obs * a.B + b] = S;
       ++n_obs;
       __syncthreads();
     }
@@ -291,6 +293,33 @@ __global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {
   if (tid == 0 && bad) atomicOr(a.flag, 1);
 }
 
+__global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  fused_body(a, blockIdx.x, smem);
+}
+
+// One launch for several contexts: the workgroup finds its context in the table (the
+// range of workgroups of each) and runs that context's trajectory with its own arguments.
+__global__ __launch_bounds__(256) void fused_group_kernel(FusedGroup grp) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int id = blockIdx.x;
+  int k = 0;
+  while (k + 1 < grp.n && id >= grp.first[k + 1]) ++k;
+  fused_body(grp.g[k], id - grp.first[k], smem);
+}
+
+hipError_t set_fused_lds_limit() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_trajectory_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_group_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
 }  // namespace
 
 size_t fused_lds_bytes(int L, int N, int Lx, int Ly) { return fused_layout(L, N, Lx, Ly).total; }
@@ -301,15 +330,26 @@ bool fused_fits(int L, int N, int Lx, int Ly) {
 }
 
 hipError_t fused_run(const FusedArgs &a, int B, hipStream_t s) {
+  if (B != a.B || !fused_fits(a.L, a.N, a.Lx, a.Ly)) return hipErrorInvalidValue;
   const size_t bytes = fused_lds_bytes(a.L, a.N, a.Lx, a.Ly);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_trajectory_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = set_fused_lds_limit();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(fused_trajectory_kernel, dim3(B), dim3(256), bytes, s, a);
+  return hipGetLastError();
+}
+
+hipError_t fused_run_group(const FusedGroup &grp, hipStream_t s) {
+  if (grp.n < 1 || grp.n > FUSED_GROUP_MAX || grp.first[0] != 0) return hipErrorInvalidValue;
+  size_t bytes = 0;
+  for (int k = 0; k < grp.n; ++k) {
+    const FusedArgs &a = grp.g[k];
+    if (grp.first[k + 1] - grp.first[k] != a.B || a.B < 1 || !fused_fits(a.L, a.N, a.Lx, a.Ly))
+      return hipErrorInvalidValue;
+    bytes = std::max(bytes, fused_lds_bytes(a.L, a.N, a.Lx, a.Ly));
+  }
+  hipError_t e = set_fused_lds_limit();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fused_group_kernel, dim3(grp.first[grp.n]), dim3(256), bytes, s, grp);
   return hipGetLastError();
 }
 

@@ -199,10 +199,20 @@ struct FusedArgs {
   int *ev_sites, *ev_out, *ev_cnt;  // projective events of the last step (L per trajectory)
   double *ev_prob;
   int *flag;
+  int B;                    // trajectories of this context (row length of S_out)
 };
 bool fused_fits(int L, int N, int Lx, int Ly);
 size_t fused_lds_bytes(int L, int N, int Lx, int Ly);
 hipError_t fused_run(const FusedArgs &a, int B, hipStream_t s);
+// Several contexts (different lattices, protocols, rates and step counts) in one launch:
+// workgroups first[k] .. first[k+1]-1 run the trajectories of ctx[k] with its own args.
+constexpr int FUSED_GROUP_MAX = 8;
+struct FusedGroup {
+  int n;
+  int first[FUSED_GROUP_MAX + 1];
+  FusedArgs g[FUSED_GROUP_MAX];
+};
+hipError_t fused_run_group(const FusedGroup &grp, hipStream_t s);
 
 // ---------------------------------------------------------------- eigen / entropy
 struct EigWork {

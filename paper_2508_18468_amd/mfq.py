@@ -41,6 +41,13 @@ class Job(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("uid", ctypes.c_uint64), ("region", ctypes.c_void_p)]
 
 
+class RunArgs(ctypes.Structure):
+    _fields_ = [("protocol", ctypes.c_int32), ("gamma", ctypes.c_void_p), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("n_steps", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("region", ctypes.c_void_p), ("n_sites", ctypes.c_int32), ("S_host", ctypes.c_void_p),
+                ("n_obs", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
                 ("n_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -97,6 +104,7 @@ _SIGS = {
     "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_propagator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_set_integrator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_run_group": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(RunArgs), ctypes.c_int32]),
     "mfq_propagator_band": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_particle_covariance": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                  ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -293,6 +301,32 @@ def mfq_run(ctx, protocol, gamma, dt, seed, n_steps, obs_every, region, n_traj, 
                               _ptr(r), r.size, _ptr(S), ctypes.byref(n_obs)))
     assert n_obs.value == n_obs_expected
     return S[:n_obs.value]
+
+
+def mfq_run_group(sims, specs):
+    """One fused launch for several Trajectories objects (mfq_run_group).  specs[k]: dict with
+    protocol, gamma, dt, seed, n_steps and optionally obs_every, region.  Returns the list of
+    S arrays (n_obs x n_traj) per context."""
+    n = len(sims)
+    ctxs = (ctypes.c_void_p * n)(*[s.ctx for s in sims])
+    args = (RunArgs * n)()
+    keep = []
+    for k, (sim, sp) in enumerate(zip(sims, specs)):
+        g = np.ascontiguousarray(np.broadcast_to(np.asarray(sp["gamma"], dtype=np.float64), (sim.n_traj,)))
+        r = _i32(sp.get("region") or [])
+        every = int(sp.get("obs_every", 0))
+        step_now = sim.step_index()
+        n_obs = (step_now + sp["n_steps"]) // every - step_now // every if every > 0 else 0
+        S = np.zeros((max(n_obs, 1), sim.n_traj))
+        keep += [g, r, S]
+        args[k] = RunArgs(int(sp["protocol"]), g.ctypes.data, float(sp["dt"]), int(sp["seed"]),
+                          int(sp["n_steps"]), every, r.ctypes.data if r.size else None, r.size,
+                          S.ctypes.data, 0)
+    code = lib().mfq_run_group(ctxs, args, n)
+    if code != MFQ_OK:
+        msgs = [lib().mfq_last_error(s.ctx).decode() for s in sims]
+        raise MfqError(code, "; ".join(m for m in msgs if m))
+    return [keep[3 * k + 2][:args[k].n_obs] for k in range(n)]
 
 
 def mfq_reset_trajectory(ctx, slot, uid):

@@ -124,3 +124,72 @@ def test_small_ring_timing(path):
         sim.close()
     print(f"{path} small-ring run: {times[-1]*1e3:.1f} ms (first {times[0]*1e3:.1f} ms); "
           f"400 homodyne steps without observation: {t_qsd*1e3:.1f} ms")
+
+
+def _group_members():
+    """Three lattices of uneven size and protocol: ring 64 projective, ring 40 homodyne, torus
+    6 x 6 homodyne (different rates, dt, seeds, step counts and observation schedules)."""
+    return [
+        dict(dim=1, Lx=64, Ly=1, uids=[3, 4, 5, 6], protocol=PM, gamma=[0.5, 0.5, 1.0, 2.0], dt=0.05,
+             seed=1, n_steps=20, obs_every=5, region=list(range(32))),
+        dict(dim=1, Lx=40, Ly=1, uids=[7, 8, 9], protocol=QSD, gamma=[0.3, 1.0, 2.5], dt=0.04, seed=2,
+             n_steps=15, obs_every=3, region=list(range(0, 40, 3))),
+        dict(dim=2, Lx=6, Ly=6, uids=[10, 11], protocol=QSD, gamma=[1.0, 0.2], dt=0.05, seed=3,
+             n_steps=10, obs_every=0, region=None),
+    ]
+
+
+def test_group_launch_equals_separate_runs_and_oracle():
+    """One launch for the three lattices equals each lattice run on its own (bitwise: same body,
+    same draws) and the homodyne ring follows the oracle (|dS| <= 1e-9)."""
+    from paper_2508_18468_amd import mfq
+    members = _group_members()
+    grouped = [make_sim(m["dim"], m["Lx"], m["Ly"], n_traj=len(m["uids"]), uids=m["uids"]) for m in members]
+    for sim in grouped:
+        sim.step(QSD, [0.4] * sim.n_traj, 0.05, 9, 2)        # a common prefix of per-phase steps
+    S_grp = mfq.mfq_run_group(grouped, members)
+    for m, sim, S in zip(members, grouped, S_grp):
+        alone = make_sim(m["dim"], m["Lx"], m["Ly"], n_traj=len(m["uids"]), uids=m["uids"])
+        alone.step(QSD, [0.4] * alone.n_traj, 0.05, 9, 2)
+        alone.set_path(mfq.PATH_FUSED)
+        S_alone = alone.run(m["protocol"], m["gamma"], m["dt"], m["seed"], m["n_steps"], m["obs_every"],
+                            m["region"])
+        assert S.shape == S_alone.shape and np.array_equal(S, S_alone)
+        assert np.array_equal(sim.get_state()[0], alone.get_state()[0])
+        assert sim.step_index() == 2 + m["n_steps"]
+        alone.close()
+    m = members[1]
+    ob = OracleBatch(1, m["Lx"], 1, 0.05, m["uids"])
+    for _ in range(2):
+        ob.step(QSD, [0.4] * 3, 9)
+    ob.dt, ob.P = m["dt"], oracle.propagator(oracle.Lattice(1, m["Lx"]), m["dt"])
+    k = 0
+    for n in range(3, 3 + m["n_steps"]):
+        ob.step(QSD, m["gamma"], m["seed"])
+        if n % m["obs_every"] == 0:
+            assert np.abs(S_grp[1][k] - ob.entropy(m["region"])).max() <= 1e-9
+            k += 1
+    assert k == S_grp[1].shape[0]
+    for sim in grouped:
+        sim.close()
+
+
+def test_group_launch_errors():
+    from paper_2508_18468_amd import mfq
+    members = _group_members()
+    sims = [make_sim(m["dim"], m["Lx"], m["Ly"], n_traj=len(m["uids"]), uids=m["uids"]) for m in members]
+    with pytest.raises(Exception):
+        mfq.mfq_run_group([sims[0], sims[0]], [members[0], members[0]])   # repeated context
+    big = make_sim(1, 1024, n_traj=1)
+    with pytest.raises(Exception):
+        mfq.mfq_run_group([sims[0], big], [members[0], dict(members[0], gamma=[0.5])])
+    sims[1].set_integrator(mfq.INTEGRATOR_RK4)
+    with pytest.raises(Exception):
+        mfq.mfq_run_group(sims[:2], members[:2])                          # RK4 is not fused
+    many = [make_sim(1, 16, n_traj=1, uids=[k]) for k in range(9)]
+    spec = dict(protocol=PM, gamma=[0.5], dt=0.05, seed=0, n_steps=1)
+    with pytest.raises(Exception):
+        mfq.mfq_run_group(many, [spec] * 9)
+    assert len(mfq.mfq_run_group(many[:8], [spec] * 8)) == 8
+    for s in sims + many + [big]:
+        s.close()
