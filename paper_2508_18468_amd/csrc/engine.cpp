@@ -8,7 +8,10 @@
 // wall time, up to the next observation or completion of one of its jobs,
 // after which finished slots are refilled from the queue.
 // Each job keeps its own random numbers (key = (seed, uid), counter = its own
-// step index), so a job gives the same result alone and in any mix.
+// step index), so a job gives the same result alone and in any mix.  Groups of small
+// lattices (state, Gram and factor in one CU's LDS, FP64) are advanced together: up to
+// eight of them, of any sizes and protocols, share one launch of the fused kernel.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -17,6 +20,7 @@
 
 #include "../../include/mfq.h"
 #include "engine_policy.h"
+#include "mfq_internal.h"
 
 using namespace mfq_serving;
 
@@ -119,6 +123,13 @@ void worker_loop(mfq_engine *e) {
       mfq_status st;
     };
     std::vector<Run> runs;
+    struct Fused {
+      int gid, k;
+      mfq_ctx *c;
+      ShapeKey key;
+      std::vector<double> gam;
+    };
+    std::vector<Fused> fused;
     for (int gid : active) {
       std::unique_lock<std::mutex> lk(e->m);
       const Group &g = e->policy.group(gid);
@@ -129,9 +140,34 @@ void worker_loop(mfq_engine *e) {
       mfq_ctx *c = e->ctx_of_group[gid];
       const ShapeKey key = g.key;
       lk.unlock();
+      const int L = key.Lx * (key.dim == 2 ? key.Ly : 1);
+      if (key.precision == MFQ_FP64 && mfq::fused_fits(L, key.N, key.Lx, key.dim == 2 ? key.Ly : 1)) {
+        fused.push_back({gid, k, c, key, std::move(gam)});
+        continue;
+      }
       const double t = e->now();
       mfq_status st = mfq_step(c, key.protocol, gam.data(), key.dt, key.seed, k);
       runs.push_back({gid, k, c, t, st});
+    }
+    // small lattices: one fused launch per (up to) FUSED_GROUP_MAX groups
+    for (size_t b0 = 0; b0 < fused.size(); b0 += mfq::FUSED_GROUP_MAX) {
+      const size_t b1 = std::min(fused.size(), b0 + (size_t)mfq::FUSED_GROUP_MAX);
+      std::vector<mfq_ctx *> cs;
+      std::vector<mfq_run_args> as;
+      for (size_t i = b0; i < b1; ++i) {
+        const Fused &f = fused[i];
+        cs.push_back(f.c);
+        mfq_run_args a{};
+        a.protocol = f.key.protocol;
+        a.gamma = f.gam.data();
+        a.dt = f.key.dt;
+        a.seed = f.key.seed;
+        a.n_steps = f.k;
+        as.push_back(a);
+      }
+      const double t = e->now();
+      const mfq_status st = mfq_run_group(cs.data(), as.data(), (int32_t)cs.size());
+      for (size_t i = b0; i < b1; ++i) runs.push_back({fused[i].gid, fused[i].k, fused[i].c, t, st});
     }
     for (Run &r : runs) {
       mfq_status st = r.st != MFQ_OK ? r.st : mfq_synchronize(r.c);
