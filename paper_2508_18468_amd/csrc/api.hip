@@ -55,6 +55,10 @@ struct mfq_ctx {
   void *rk_buf = nullptr;   // RK4 scratch (a third state buffer and the diagonal), on first use
   size_t rk_cap = 0;
   bool ct_any = false;  // an event batch has run since mfq_init_state
+  int ct_block = 0;     // deferred events per block on rings (0: event by event)
+  BlockWork bw{};
+  void *blk_buf = nullptr;
+  size_t blk_cap = 0;
   std::vector<double> gamma_host;
   // phase timing
   bool profiling = false;
@@ -578,6 +582,7 @@ mfq_status mfq_destroy(mfq_ctx *c) {
   if (c->run_S) (void)hipFree(c->run_S);
   if (c->red_buf) (void)hipFree(c->red_buf);
   if (c->rk_buf) (void)hipFree(c->rk_buf);
+  if (c->blk_buf) (void)hipFree(c->blk_buf);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -703,6 +708,37 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
   return MFQ_OK;
 }
 
+// Scratch of the deferred events (per trajectory WL, WR, Zc, G, T1 and the block clock),
+// allocated on first use; the block clocks start at zero.
+mfq_status ensure_blk(mfq_ctx *c) {
+  const long K = c->ct_block, L = c->L, N = c->N, B = c->B;
+  const size_t cpl = align_up((size_t)(5 * N * K + 3 * L * K) * B * sizeof(cplx));
+  const size_t need = cpl + (size_t)B * sizeof(double);
+  if (c->blk_cap < need) {
+    if (c->blk_buf) {
+      HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+      (void)hipFree(c->blk_buf);
+      c->blk_buf = nullptr;
+      c->blk_cap = 0;
+    }
+    if (hipMalloc(&c->blk_buf, need) != hipSuccess) {
+      c->blk_buf = nullptr;
+      return fail(c, MFQ_ENOMEM, "hipMalloc of the deferred-event scratch failed");
+    }
+    c->blk_cap = need;
+  }
+  cplx *p = reinterpret_cast<cplx *>(c->blk_buf);
+  c->bw.WL = p; p += 2 * N * K * B;
+  c->bw.WR = p; p += 2 * N * K * B;
+  c->bw.Zc = p; p += N * K * B;
+  c->bw.G = p; p += L * K * B;
+  c->bw.T1 = p;
+  c->bw.s = reinterpret_cast<double *>(reinterpret_cast<char *>(c->blk_buf) + cpl);
+  c->bw.K = (int)K;
+  HIPCHK(fill_zero(c->bw.s, (size_t)B * sizeof(double), c->stream), "block clock clear");
+  return MFQ_OK;
+}
+
 mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t n_events, double t_end,
                          int32_t reorth_every) {
   if (!c) return MFQ_EINVAL;
@@ -724,6 +760,40 @@ mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t
   }
   HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
   const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+  if (c->ct_block > 0 && c->lat.dim == 1) {  // deferred events, flushed every ct_block slots
+    mfq_status st = ensure_blk(c);
+    if (st) return st;
+    int e = 0;
+    for (int slot = 0; slot < n_events; ++slot) {
+      {
+        PhaseTimer t(c, MFQ_PHASE_MEASURE);
+        HIPCHK(cont_block_event(c->X[c->cur], c->L, c->N, c->B, e, c->lat.J, c->gamma, t_end, seed, c->uid,
+                                c->step_dev, 1, c->step_base, c->ct, c->bw, c->stream), "deferred event");
+      }
+      ++e;
+      HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
+      c->step += 1;
+      c->ct_any = true;
+      const bool reorth = reorth_every > 0 && c->step % reorth_every == 0;
+      if (e == c->ct_block || slot + 1 == n_events || reorth) {
+        {
+          PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
+          HIPCHK(cont_block_flush(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, e, c->lat.J, c->ct, c->bw,
+                                  c->stream), "deferred events flush");
+        }
+        c->cur = 1 - c->cur;
+        e = 0;
+      }
+      if (reorth) {
+        PhaseTimer t(c, MFQ_PHASE_REORTH);
+        HIPCHK(cholqr_pass(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, false, c->stream),
+               "cholqr pass 1");
+        HIPCHK(cholqr_pass(c->X[1 - c->cur], c->X[c->cur], c->L, c->N, c->B, c->chol, true, c->stream),
+               "cholqr pass 2");
+      }
+    }
+    return MFQ_OK;
+  }
   for (int e = 0; e < n_events; ++e) {
     bool in_b = false;
     {
@@ -792,6 +862,13 @@ mfq_status mfq_set_times(mfq_ctx *c, const double *t_host) {
   HIPCHK(hipMemcpyAsync(c->ct.t, t_host, c->B * sizeof(double), hipMemcpyHostToDevice, c->stream),
          "clock upload");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return MFQ_OK;
+}
+
+mfq_status mfq_set_ct_block(mfq_ctx *c, int32_t block) {
+  if (!c) return MFQ_EINVAL;
+  if (block < 0 || block > 64) return fail(c, MFQ_EINVAL, "block length must be in 0 .. 64");
+  c->ct_block = block;
   return MFQ_OK;
 }
 

@@ -412,12 +412,13 @@ __global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D,
 // (the halo wraps around the ring), then each thread forms its row of P U for the eight
 // columns from LDS (lanes read consecutive rows: no bank conflicts), subtracts yp v^+
 // and fixes row j / column 0 like cont_apply_kernel<true>.
+template <bool UPDATE>
 __global__ __launch_bounds__(256) void cont_ring_kernel(const cplx *U, cplx *D, int L, int N, int nrb,
-                                                        ContWork w) {
+                                                        int band_slot, ContWork w) {
   const int b = blockIdx.y;
   const int rb = blockIdx.x % nrb, cb = blockIdx.x / nrb;
   const int *info = w.info + 4 * b;
-  const int band = info[2];
+  const int band = info[band_slot];
   if (!ring_lds_band(band, L)) return;
   __shared__ cplx s[RING_CT][RING_ROWS + 2 * RING_WMAX];
   __shared__ cplx gs[2 * RING_WMAX + 1];
@@ -454,10 +455,16 @@ __global__ __launch_bounds__(256) void cont_ring_kernel(const cplx *U, cplx *D, 
       ai[c] += gv.re * u.im + gv.im * u.re;
     }
   }
+  cplx *Db = D + (long)b * L * N;
+  if (!UPDATE) {  // the band alone (the deferred propagation of a block of events)
+#pragma unroll
+    for (int c = 0; c < RING_CT; ++c)
+      if (c < nk) Db[i + (long)(k0 + c) * L] = cplx{ar[c], ai[c]};
+    return;
+  }
   const int j = info[0], outcome = info[1];
   const cplx yi = w.yp[(long)b * L + i];
   const cplx *v = w.v + (long)b * N;
-  cplx *Db = D + (long)b * L * N;
 #pragma unroll
   for (int c = 0; c < RING_CT; ++c) {
     if (c >= nk) break;
@@ -492,6 +499,268 @@ __global__ __launch_bounds__(256) void cont_norm_kernel(cplx *U, int L, int N, C
   if (!(n0 > 0.0)) return;
   const double sc = 1.0 / sqrt(n0);
   for (int i = threadIdx.x; i < L; i += 256) c0[i] = cplx{c0[i].re * sc, c0[i].im * sc};
+}
+
+// ---- deferred events on the ring (blocks of up to K events) ----
+// Within a block every event is taken back to the block's start (all propagators commute):
+// the state is V = V0 (I + WL WR^+) + G Z with U = P(s) V, s the time since the block's start.
+// Event e (0-based in the block) reads the combined row r = sum_d g_s[d] V[j - d, :] =
+// u (I + WL WR^+) + sum_f gamma_f z_f, u = sum_d g_s[d] V0[j - d, :], gamma_f = sum_d g_s[d]
+// G[j - d, f]; its projection is the factor D_e = (I - tau v v^+)(I + delta e0 e0^T) =
+// I + X Y^+ with X = [-tau v, delta (e0 - tau conj(v0) v)], Y = [v, e0], followed by the
+// additive term g_e c_e e0^T, g_e = P(-s) e_j (the band conj(g_s[i - j]) around j):
+// outcome 1: delta = -1, c_e = 1; outcome 0: delta = 1/nu - 1, c_e = -conj(alpha)/nu,
+// nu = sqrt(1 - p_j), alpha the reflector's image of x = conj(r).  Hence WL gains the
+// columns X + WL (WR^+ X), WR the columns Y, every earlier z_f the term (z_f X) Y^+ and
+// z_e = c_e e0^T.  Storage per trajectory, column-major: WL, WR N x 2K; Zc = conj(Z)^T N x K;
+// G L x K.  One workgroup per trajectory; O((2w + 1) N + N e) work per event.
+struct BlockArgs {
+  const cplx *U;
+  int L, N, e;
+  double J;
+  const double *gamma;
+  double t_end;
+  uint64_t seed;
+  const uint64_t *uid;
+  const int64_t *step_ptr;
+  int step_offset;
+  const int64_t *step_base;
+  ContWork w;
+  BlockWork bw;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+constexpr int BLOCK_KMAX = 64;
+
+__global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int L = a.L, N = a.N, K = a.bw.K, e = a.e;
+  cplx *WL = a.bw.WL + (long)b * N * 2 * K;
+  cplx *WR = a.bw.WR + (long)b * N * 2 * K;
+  cplx *Zc = a.bw.Zc + (long)b * N * K;
+  cplx *G = a.bw.G + (long)b * L * K;
+  int *info = a.w.info + 4 * b;
+  double *dinfo = a.w.dinfo + 4 * b;
+  for (int i = tid; i < L; i += 256) G[i + (long)e * L] = cplx{0.0, 0.0};
+  const double t0 = a.w.t[b];
+  if (!(t0 < a.t_end)) {  // no event: the factor is the identity, no additive term
+    for (int k = tid; k < N; k += 256) {
+      WL[k + (long)(2 * e) * N] = WL[k + (long)(2 * e + 1) * N] = cplx{0.0, 0.0};
+      WR[k + (long)(2 * e) * N] = WR[k + (long)(2 * e + 1) * N] = cplx{0.0, 0.0};
+      Zc[k + (long)e * N] = cplx{0.0, 0.0};
+    }
+    if (tid == 0) {
+      info[0] = -1; info[1] = 0; info[2] = -1;
+      dinfo[0] = 0.0; dinfo[1] = 0.0; dinfo[2] = 0.0;
+    }
+    return;
+  }
+  __shared__ double sh_tau, sh_pc, red[4];
+  __shared__ int sh_j, sh_w, sh_out;
+  __shared__ cplx sh_q[2 * BLOCK_KMAX], sh_gam[BLOCK_KMAX], sh_h[2 * BLOCK_KMAX][2], sh_a[BLOCK_KMAX][2];
+  __shared__ double sh_tauh, sh_delta;
+  __shared__ cplx sh_c;
+  if (tid == 0) {
+    const uint64_t n = (uint64_t)(*a.step_ptr + a.step_offset - a.step_base[b]);
+    const u64x4 r = philox4x64_10(a.seed, a.uid[b], n, 0, PURPOSE_CONTINUOUS, 0);
+    sh_tau = -log(u01(r.v[0])) / (a.gamma[b] * N);
+    sh_j = (int)__umul64hi(r.v[1], (uint64_t)L);
+    sh_pc = u01(r.v[2]);
+  }
+  __syncthreads();
+  const double tau = sh_tau, s_new = a.bw.s[b] + tau;
+  const int j = sh_j;
+  cplx *g = a.w.g + (long)b * (L + 1);
+  double *jn = a.w.jn + (long)b * a.w.jcap;
+  const int wb = ring_row_dev(2.0 * a.J * s_new, L, g, jn, a.w.jcap, &sh_w);
+  const Taps t = taps_of(wb, L);
+  const cplx *V0 = a.U + (long)b * L * N;
+  cplx *x = a.w.v + (long)b * N;  // u, then x = conj(r), then the scaled reflector
+  for (int k = tid; k < N; k += 256) {
+    const cplx *Vk = V0 + (long)k * L;
+    double ur = 0.0, ui = 0.0;
+    for (int d = t.lo; d <= t.hi; ++d) {
+      const cplx gv = g[wrap(d, L)], v = Vk[wrap(j - d, L)];
+      ur += gv.re * v.re - gv.im * v.im;
+      ui += gv.re * v.im + gv.im * v.re;
+    }
+    x[k] = cplx{ur, ui};
+  }
+  for (int f = tid; f < e; f += 256) {
+    const cplx *Gf = G + (long)f * L;
+    double gr = 0.0, gi = 0.0;
+    for (int d = t.lo; d <= t.hi; ++d) {
+      const cplx gv = g[wrap(d, L)], v = Gf[wrap(j - d, L)];
+      gr += gv.re * v.re - gv.im * v.im;
+      gi += gv.re * v.im + gv.im * v.re;
+    }
+    sh_gam[f] = cplx{gr, gi};
+  }
+  __syncthreads();
+  // q = u WL (one wave per column, lanes over rows)
+  for (int c = wave; c < 2 * e; c += 4) {
+    const cplx *Wc = WL + (long)c * N;
+    double qr = 0.0, qi = 0.0;
+    for (int k = lane; k < N; k += 64) {
+      const cplx u = x[k], w = Wc[k];
+      qr += u.re * w.re - u.im * w.im;
+      qi += u.re * w.im + u.im * w.re;
+    }
+    qr = wave_sum(qr);
+    qi = wave_sum(qi);
+    if (lane == 0) sh_q[c] = cplx{qr, qi};
+  }
+  __syncthreads();
+  // r = u + q WR^+ + sum_f gamma_f z_f; x = conj(r); p = |r|^2
+  double part = 0.0, mx = 0.0;
+  for (int k = tid; k < N; k += 256) {
+    cplx r = x[k];
+    for (int c = 0; c < 2 * e; ++c) {  // + q_c conj(WR[k, c])
+      const cplx q = sh_q[c], w = WR[k + (long)c * N];
+      r.re += q.re * w.re + q.im * w.im;
+      r.im += q.im * w.re - q.re * w.im;
+    }
+    for (int f = 0; f < e; ++f) {  // + gamma_f z_f[k], z_f[k] = conj(Zc[k, f])
+      const cplx gm = sh_gam[f], z = Zc[k + (long)f * N];
+      r.re += gm.re * z.re + gm.im * z.im;
+      r.im += gm.im * z.re - gm.re * z.im;
+    }
+    x[k] = cplx{r.re, -r.im};
+    part += r.re * r.re + r.im * r.im;
+    mx = fmax(mx, fmax(fabs(r.re), fabs(r.im)));
+  }
+  const double p = block_sum256(part, red);
+  const double smax = block_max256(mx, red);
+  double part2 = 0.0;
+  if (smax >= REFLECT_TINY) {
+    const double inv = 1.0 / smax;
+    for (int k = tid; k < N; k += 256) {
+      const cplx q{x[k].re * inv, x[k].im * inv};
+      x[k] = q;
+      if (k >= 1) part2 += q.re * q.re + q.im * q.im;
+    }
+  }
+  const double tail2 = block_sum256(part2, red);
+  if (tid == 0) {
+    double tau_h = 0.0;
+    cplx alpha_c{0.0, 0.0};  // conj(alpha), alpha = -phase(x0) |x|
+    if (smax >= REFLECT_TINY) {
+      const cplx x0 = x[0];
+      const Reflector h = make_reflector(x0, tail2, smax);
+      const double ax0 = hypot(x0.re, x0.im);
+      const double phr = ax0 > 0.0 ? x0.re / ax0 : 1.0, phi = ax0 > 0.0 ? x0.im / ax0 : 0.0;
+      alpha_c = cplx{-phr * h.norm, phi * h.norm};
+      x[0] = h.v0;
+      tau_h = h.tau;
+    } else {
+      for (int k = 0; k < N; ++k) x[k] = cplx{0.0, 0.0};
+    }
+    const int outcome = (sh_pc <= p) ? 1 : 0;
+    sh_out = outcome;
+    sh_tauh = tau_h;
+    if (outcome == 1) {
+      sh_delta = -1.0;
+      sh_c = cplx{1.0, 0.0};
+    } else {
+      const double nu = sqrt(fmax(1.0 - p, 1e-300));
+      sh_delta = 1.0 / nu - 1.0;
+      sh_c = cplx{-alpha_c.re / nu, -alpha_c.im / nu};
+    }
+    info[0] = j; info[1] = outcome; info[2] = wb;
+    dinfo[0] = tau; dinfo[1] = p; dinfo[2] = tau_h;
+  }
+  __syncthreads();
+  const double th = sh_tauh, dl = sh_delta;
+  const cplx v0 = x[0];
+  // X[k] = (-th v_k, dl (delta_k0 - th conj(v0) v_k))
+  auto Xk = [&](int k, int m) -> cplx {
+    const cplx v = x[k];
+    if (m == 0) return cplx{-th * v.re, -th * v.im};
+    // conj(v0) v
+    const double cr = v0.re * v.re + v0.im * v.im, ci = v0.re * v.im - v0.im * v.re;
+    return cplx{dl * ((k == 0 ? 1.0 : 0.0) - th * cr), -dl * th * ci};
+  };
+  // h = WR^+ X (2e x 2) and a_f = z_f X (e x 2), z_f[k] = conj(Zc[k, f])
+  for (int c = wave; c < 2 * e + e; c += 4) {
+    const bool isW = c < 2 * e;
+    const cplx *col = isW ? WR + (long)c * N : Zc + (long)(c - 2 * e) * N;
+    double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
+    for (int k = lane; k < N; k += 64) {
+      const cplx w = col[k];  // conj(w) X for both (WR^+ and conj(Zc))
+      const cplx X0 = Xk(k, 0), X1 = Xk(k, 1);
+      r0 += w.re * X0.re + w.im * X0.im;
+      i0 += w.re * X0.im - w.im * X0.re;
+      r1 += w.re * X1.re + w.im * X1.im;
+      i1 += w.re * X1.im - w.im * X1.re;
+    }
+    r0 = wave_sum(r0); i0 = wave_sum(i0); r1 = wave_sum(r1); i1 = wave_sum(i1);
+    if (lane == 0) {
+      if (isW) {
+        sh_h[c][0] = cplx{r0, i0};
+        sh_h[c][1] = cplx{r1, i1};
+      } else {
+        sh_a[c - 2 * e][0] = cplx{r0, i0};
+        sh_a[c - 2 * e][1] = cplx{r1, i1};
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < N; k += 256) {
+    // WL columns 2e, 2e+1: X + WL h
+    cplx n0 = Xk(k, 0), n1 = Xk(k, 1);
+    for (int c = 0; c < 2 * e; ++c) {
+      const cplx w = WL[k + (long)c * N], h0 = sh_h[c][0], h1 = sh_h[c][1];
+      n0.re += w.re * h0.re - w.im * h0.im;
+      n0.im += w.re * h0.im + w.im * h0.re;
+      n1.re += w.re * h1.re - w.im * h1.im;
+      n1.im += w.re * h1.im + w.im * h1.re;
+    }
+    WL[k + (long)(2 * e) * N] = n0;
+    WL[k + (long)(2 * e + 1) * N] = n1;
+    const cplx vk = x[k];
+    WR[k + (long)(2 * e) * N] = vk;
+    WR[k + (long)(2 * e + 1) * N] = cplx{k == 0 ? 1.0 : 0.0, 0.0};
+    // earlier additive rows: z_f += a_f0 conj(Y0) + a_f1 conj(Y1), stored conjugated
+    for (int f = 0; f < e; ++f) {
+      const cplx a0 = sh_a[f][0], a1 = sh_a[f][1];
+      cplx z = Zc[k + (long)f * N];
+      // + conj(a0) v_k + conj(a1) delta_k0
+      z.re += a0.re * vk.re + a0.im * vk.im;
+      z.im += a0.re * vk.im - a0.im * vk.re;
+      if (k == 0) {
+        z.re += a1.re;
+        z.im -= a1.im;
+      }
+      Zc[k + (long)f * N] = z;
+    }
+    Zc[k + (long)e * N] = k == 0 ? cplx{sh_c.re, -sh_c.im} : cplx{0.0, 0.0};
+  }
+  // g_e = P(-s) e_j: G[j + d, e] = conj(g[d]) over the band
+  for (int d = t.lo + tid; d <= t.hi; d += 256) {
+    const cplx gv = g[wrap(d, L)];
+    G[wrap(j + d, L) + (long)e * L] = cplx{gv.re, -gv.im};
+  }
+  if (tid == 0) {
+    a.bw.s[b] = s_new;
+    a.w.t[b] = t0 + tau;
+  }
+}
+
+// Ring rows of P(s) for the time accumulated since the block's start (band in info[3]);
+// the block clock restarts.
+__global__ __launch_bounds__(256) void cont_block_rows_kernel(int L, double J, ContWork w, BlockWork bw) {
+  const int b = blockIdx.x;
+  __shared__ int sh_w;
+  const double sb = bw.s[b];
+  const int wb = ring_row_dev(2.0 * J * sb, L, w.g + (long)b * (L + 1), w.jn + (long)b * w.jcap, w.jcap, &sh_w);
+  if (threadIdx.x == 0) {
+    w.info[4 * b + 3] = wb;
+    bw.s[b] = 0.0;
+  }
 }
 
 __global__ void clock_set_kernel(double *t, int first, int count, double value) {
@@ -532,8 +801,8 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
     // narrow bands through LDS; wide bands, full rows and trajectories without an event
     // by the direct pass, whose few workgroups per trajectory exit at once otherwise
     const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
-    hipLaunchKernelGGL(cont_ring_kernel, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua, Ub,
-                       L, N, rnb, w);
+    hipLaunchKernelGGL(cont_ring_kernel<true>, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua,
+                       Ub, L, N, rnb, 2, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 few((unsigned)std::min(ntiles, 8), B);
     hipLaunchKernelGGL(cont_apply_kernel<true>, few, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0, 2,
@@ -552,6 +821,65 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(cont_norm_kernel, dim3(B), dim3(256), 0, s, out, L, N, w);
+  return hipGetLastError();
+}
+
+hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, double J, const double *gamma,
+                            double t_end, uint64_t seed, const uint64_t *uid, const int64_t *step_ptr,
+                            int step_offset, const int64_t *step_base, const ContWork &w, const BlockWork &bw,
+                            hipStream_t s) {
+  if (bw.K < 1 || bw.K > BLOCK_KMAX || e < 0 || e >= bw.K || N < 1 || B < 1) return hipErrorInvalidValue;
+  BlockArgs a{U, L, N, e, J, gamma, t_end, seed, uid, step_ptr, step_offset, step_base, w, bw};
+  hipLaunchKernelGGL(cont_block_event_kernel, dim3(B), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, double J, const ContWork &w,
+                            const BlockWork &bw, hipStream_t s) {
+  if (e < 1 || e > bw.K) return hipErrorInvalidValue;
+  const int K = bw.K;
+  hipError_t err;
+  {  // T1 = V0 WL
+    GemmDesc g{};
+    g.alpha = cplx{1.0, 0.0};
+    g.M = L; g.N = 2 * e; g.K = N; g.batch = B;
+    g.A = Ua; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
+    g.B = bw.WL; g.ldb = N; g.sB = (long)N * 2 * K; g.opB = OP_N;
+    g.D = bw.T1; g.ldd = L; g.sD = (long)L * 2 * K;
+    if ((err = zgemm(g, s)) != hipSuccess) return err;
+  }
+  {  // V0 += T1 WR^+  (in place: each entry is read and written by one thread)
+    GemmDesc g{};
+    g.alpha = cplx{1.0, 0.0};
+    g.beta = cplx{1.0, 0.0};
+    g.M = L; g.N = N; g.K = 2 * e; g.batch = B;
+    g.A = bw.T1; g.lda = L; g.sA = (long)L * 2 * K; g.opA = OP_N;
+    g.B = bw.WR; g.ldb = N; g.sB = (long)N * 2 * K; g.opB = OP_C;
+    g.Cin = Ua; g.ldcin = L; g.sCin = (long)L * N;
+    g.D = Ua; g.ldd = L; g.sD = (long)L * N;
+    if ((err = zgemm(g, s)) != hipSuccess) return err;
+  }
+  {  // V0 += G Z, Z = Zc^+
+    GemmDesc g{};
+    g.alpha = cplx{1.0, 0.0};
+    g.beta = cplx{1.0, 0.0};
+    g.M = L; g.N = N; g.K = e; g.batch = B;
+    g.A = bw.G; g.lda = L; g.sA = (long)L * K; g.opA = OP_N;
+    g.B = bw.Zc; g.ldb = N; g.sB = (long)N * K; g.opB = OP_C;
+    g.Cin = Ua; g.ldcin = L; g.sCin = (long)L * N;
+    g.D = Ua; g.ldd = L; g.sD = (long)L * N;
+    if ((err = zgemm(g, s)) != hipSuccess) return err;
+  }
+  // U = P(s) V: the rows for each trajectory's time since the block's start, then the band
+  hipLaunchKernelGGL(cont_block_rows_kernel, dim3(B), dim3(256), 0, s, L, J, w, bw);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
+  hipLaunchKernelGGL(cont_ring_kernel<false>, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua, Ub,
+                     L, N, rnb, 3, w);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  const int nrb = (L + 63) / 64, ncb = (N + 4 * CONT_CPW - 1) / (4 * CONT_CPW), ntiles = nrb * ncb;
+  hipLaunchKernelGGL(cont_apply_kernel<false>, dim3((unsigned)std::min(ntiles, 8), B), dim3(256), 0, s,
+                     (const cplx *)Ua, Ub, L, N, 1, L, 0, 3, nrb, ntiles, L, 1, 1, w);
   return hipGetLastError();
 }
 

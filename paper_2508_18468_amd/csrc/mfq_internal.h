@@ -145,6 +145,26 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
                       const int64_t *step_ptr, int step_offset, const int64_t *step_base,
                       const ContWork &w, bool *state_in_b, hipStream_t s);
 
+// Deferred events on the ring: blocks of up to K (<= 64) events kept in factored form
+// (V = V0 (I + WL WR^+) + G Z, taken back to the block's start) and applied by cont_block_flush.
+struct BlockWork {
+  cplx *WL, *WR;  // N x 2K per trajectory
+  cplx *Zc;       // N x K per trajectory (conj(Z)^T)
+  cplx *G;        // L x K per trajectory
+  cplx *T1;       // L x 2K per trajectory (flush scratch)
+  double *s;      // B: time since the block's start
+  int K;
+};
+// Event e (0-based) of the current block for every trajectory with clock below t_end; U (the
+// state at the block's start) is only read.
+hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, double J, const double *gamma,
+                            double t_end, uint64_t seed, const uint64_t *uid, const int64_t *step_ptr,
+                            int step_offset, const int64_t *step_base, const ContWork &w, const BlockWork &bw,
+                            hipStream_t s);
+// Apply the block's e events: Ua (block start) is overwritten by V, Ub receives U = P(s) V.
+hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, double J, const ContWork &w,
+                            const BlockWork &bw, hipStream_t s);
+
 // ---------------------------------------------------------------- RK4 homodyne step
 // Appendix A: the homodyne step with Eq. (A4)'s exponent frozen over the step and
 // integrated by RK4 (the degree-4 Taylor polynomial of exp(A), in Horner form).

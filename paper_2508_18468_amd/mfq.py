@@ -87,6 +87,7 @@ _SIGS = {
     "mfq_ct_last_events": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_get_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_set_ct_block": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_set_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_get_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mfq_set_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
@@ -508,6 +509,10 @@ class Trajectories:
         """Continuous-time projective protocol: n_events event slots (mfq_ct_events)."""
         g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (self.n_traj,))
         mfq_ct_events(self.ctx, g, seed, n_events, t_end, reorth_every)
+
+    def set_ct_block(self, block):
+        """Deferred continuous-time events on rings: blocks of `block` events (0: one by one)."""
+        _check(self.ctx, lib().mfq_set_ct_block(self.ctx, int(block)))
 
     def ct_last_events(self):
         """(site, outcome, p, tau) per trajectory for the latest event slot (site -1: none)."""

@@ -186,3 +186,61 @@ def test_full_size_ring():
     for b in range(B):
         assert np.abs(U[b].conj().T @ U[b] - np.eye(L // 2)).max() <= 1e-12
     sim.close()
+
+
+@pytest.mark.parametrize("L,gammas,n_slots,K,reorth,t_end", [
+    (64, [0.3, 1.0, 2.5], 60, 1, 0, np.inf),
+    (64, [0.3, 1.0, 2.5], 60, 16, 0, np.inf),
+    (200, [0.7, 4.0], 40, 5, 8, np.inf),       # ragged tiles, Cholesky-QR inside blocks
+    (200, [0.001, 0.7], 12, 64, 0, np.inf),    # wide bands
+    (32, [0.5, 2.0], 40, 16, 0, 0.4),          # trajectories stop inside a block
+])
+def test_deferred_events_equal_event_by_event_and_oracle(L, gammas, n_slots, K, reorth, t_end):
+    """Blocks of K deferred events (one call of n_slots slots) against the same slots taken one
+    by one and against the oracle: same last events, same clocks, C to 2e-11."""
+    B, seed = len(gammas), 23
+    uids = [4 + 3 * b for b in range(B)]
+    blk = make_sim(1, L, n_traj=B, uids=uids)
+    one = make_sim(1, L, n_traj=B, uids=uids)
+    blk.set_ct_block(K)
+    blk.ct_events(gammas, seed, n_slots, t_end=t_end, reorth_every=reorth)
+    one.ct_events(gammas, seed, n_slots, t_end=t_end, reorth_every=reorth)
+    orc = OracleCT(1, L, 1, uids, gammas, seed)
+    for _ in range(n_slots):
+        recs = orc.slot(t_end)
+    _check_slot(blk, orc, recs)
+    sb, ob, pb, tb = blk.ct_last_events()
+    so, oo, po, to = one.ct_last_events()
+    assert np.array_equal(sb, so) and np.array_equal(ob, oo)
+    assert np.allclose(blk.times(), one.times(), rtol=1e-13, atol=0.0)
+    Ub, _ = blk.get_state()
+    Uo, _ = one.get_state()
+    for b in range(B):
+        assert np.abs(corr(Ub[b]) - corr(Uo[b])).max() <= 2e-11
+    _check_state(blk, orc)
+    blk.close()
+    one.close()
+
+
+def test_deferred_events_full_size():
+    """Ring L = 1024, N = 512, 8 trajectories: 96 slots in blocks of 32 against the same slots
+    one by one (C to 1e-10, identical last events); orthonormality kept."""
+    L, B, seed = 1024, 8, 9
+    gammas = list(np.linspace(0.1, 1.0, B))
+    uids = list(range(40, 40 + B))
+    blk = make_sim(1, L, n_traj=B, uids=uids)
+    one = make_sim(1, L, n_traj=B, uids=uids)
+    blk.set_ct_block(32)
+    blk.ct_events(gammas, seed, 96)
+    one.ct_events(gammas, seed, 96)
+    assert np.array_equal(blk.ct_last_events()[0], one.ct_last_events()[0])
+    assert np.array_equal(blk.ct_last_events()[1], one.ct_last_events()[1])
+    Ub, _ = blk.get_state()
+    Uo, _ = one.get_state()
+    for b in range(B):
+        assert np.abs(corr(Ub[b]) - corr(Uo[b])).max() <= 1e-10
+        assert np.abs(Ub[b].conj().T @ Ub[b] - np.eye(L // 2)).max() <= 1e-12
+    with pytest.raises(Exception):
+        blk.set_ct_block(65)
+    blk.close()
+    one.close()
