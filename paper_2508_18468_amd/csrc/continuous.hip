@@ -535,8 +535,38 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int BLOCK_KMAX = 64;
+constexpr int BLOCK_EVENT_THREADS = 1024;
 
-__global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
+// Sum / max over the NT threads of a workgroup (wave shuffles, then the wave partials in a
+// fixed order); every thread receives the result.
+template <int NT>
+__device__ __forceinline__ double block_sum_nt(double v, double *red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) s += red[q];
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_max_nt(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double m = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) m = fmax(m, red[q]);
+  return m;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
+  constexpr int NW = NT / 64;
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int L = a.L, N = a.N, K = a.bw.K, e = a.e;
   cplx *WL = a.bw.WL + (long)b * N * 2 * K;
@@ -545,10 +575,10 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
   cplx *G = a.bw.G + (long)b * L * K;
   int *info = a.w.info + 4 * b;
   double *dinfo = a.w.dinfo + 4 * b;
-  for (int i = tid; i < L; i += 256) G[i + (long)e * L] = cplx{0.0, 0.0};
+  for (int i = tid; i < L; i += NT) G[i + (long)e * L] = cplx{0.0, 0.0};
   const double t0 = a.w.t[b];
   if (!(t0 < a.t_end)) {  // no event: the factor is the identity, no additive term
-    for (int k = tid; k < N; k += 256) {
+    for (int k = tid; k < N; k += NT) {
       WL[k + (long)(2 * e) * N] = WL[k + (long)(2 * e + 1) * N] = cplx{0.0, 0.0};
       WR[k + (long)(2 * e) * N] = WR[k + (long)(2 * e + 1) * N] = cplx{0.0, 0.0};
       Zc[k + (long)e * N] = cplx{0.0, 0.0};
@@ -559,7 +589,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     }
     return;
   }
-  __shared__ double sh_tau, sh_pc, red[4];
+  __shared__ double sh_tau, sh_pc, red[NW];
   __shared__ int sh_j, sh_w, sh_out;
   __shared__ cplx sh_q[2 * BLOCK_KMAX], sh_gam[BLOCK_KMAX], sh_h[2 * BLOCK_KMAX][2], sh_a[BLOCK_KMAX][2];
   __shared__ double sh_tauh, sh_delta;
@@ -580,7 +610,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
   const Taps t = taps_of(wb, L);
   const cplx *V0 = a.U + (long)b * L * N;
   cplx *x = a.w.v + (long)b * N;  // u, then x = conj(r), then the scaled reflector
-  for (int k = tid; k < N; k += 256) {
+  for (int k = tid; k < N; k += NT) {
     const cplx *Vk = V0 + (long)k * L;
     double ur = 0.0, ui = 0.0;
     for (int d = t.lo; d <= t.hi; ++d) {
@@ -590,7 +620,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     }
     x[k] = cplx{ur, ui};
   }
-  for (int f = tid; f < e; f += 256) {
+  for (int f = tid; f < e; f += NT) {
     const cplx *Gf = G + (long)f * L;
     double gr = 0.0, gi = 0.0;
     for (int d = t.lo; d <= t.hi; ++d) {
@@ -602,7 +632,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
   }
   __syncthreads();
   // q = u WL (one wave per column, lanes over rows)
-  for (int c = wave; c < 2 * e; c += 4) {
+  for (int c = wave; c < 2 * e; c += NW) {
     const cplx *Wc = WL + (long)c * N;
     double qr = 0.0, qi = 0.0;
     for (int k = lane; k < N; k += 64) {
@@ -617,7 +647,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
   __syncthreads();
   // r = u + q WR^+ + sum_f gamma_f z_f; x = conj(r); p = |r|^2
   double part = 0.0, mx = 0.0;
-  for (int k = tid; k < N; k += 256) {
+  for (int k = tid; k < N; k += NT) {
     cplx r = x[k];
     for (int c = 0; c < 2 * e; ++c) {  // + q_c conj(WR[k, c])
       const cplx q = sh_q[c], w = WR[k + (long)c * N];
@@ -633,18 +663,18 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     part += r.re * r.re + r.im * r.im;
     mx = fmax(mx, fmax(fabs(r.re), fabs(r.im)));
   }
-  const double p = block_sum256(part, red);
-  const double smax = block_max256(mx, red);
+  const double p = block_sum_nt<NT>(part, red);
+  const double smax = block_max_nt<NT>(mx, red);
   double part2 = 0.0;
   if (smax >= REFLECT_TINY) {
     const double inv = 1.0 / smax;
-    for (int k = tid; k < N; k += 256) {
+    for (int k = tid; k < N; k += NT) {
       const cplx q{x[k].re * inv, x[k].im * inv};
       x[k] = q;
       if (k >= 1) part2 += q.re * q.re + q.im * q.im;
     }
   }
-  const double tail2 = block_sum256(part2, red);
+  const double tail2 = block_sum_nt<NT>(part2, red);
   if (tid == 0) {
     double tau_h = 0.0;
     cplx alpha_c{0.0, 0.0};  // conj(alpha), alpha = -phase(x0) |x|
@@ -685,7 +715,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     return cplx{dl * ((k == 0 ? 1.0 : 0.0) - th * cr), -dl * th * ci};
   };
   // h = WR^+ X (2e x 2) and a_f = z_f X (e x 2), z_f[k] = conj(Zc[k, f])
-  for (int c = wave; c < 2 * e + e; c += 4) {
+  for (int c = wave; c < 2 * e + e; c += NW) {
     const bool isW = c < 2 * e;
     const cplx *col = isW ? WR + (long)c * N : Zc + (long)(c - 2 * e) * N;
     double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0;
@@ -709,7 +739,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     }
   }
   __syncthreads();
-  for (int k = tid; k < N; k += 256) {
+  for (int k = tid; k < N; k += NT) {
     // WL columns 2e, 2e+1: X + WL h
     cplx n0 = Xk(k, 0), n1 = Xk(k, 1);
     for (int c = 0; c < 2 * e; ++c) {
@@ -740,7 +770,7 @@ __global__ __launch_bounds__(256) void cont_block_event_kernel(BlockArgs a) {
     Zc[k + (long)e * N] = k == 0 ? cplx{sh_c.re, -sh_c.im} : cplx{0.0, 0.0};
   }
   // g_e = P(-s) e_j: G[j + d, e] = conj(g[d]) over the band
-  for (int d = t.lo + tid; d <= t.hi; d += 256) {
+  for (int d = t.lo + tid; d <= t.hi; d += NT) {
     const cplx gv = g[wrap(d, L)];
     G[wrap(j + d, L) + (long)e * L] = cplx{gv.re, -gv.im};
   }
@@ -830,7 +860,7 @@ hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, double J,
                             hipStream_t s) {
   if (bw.K < 1 || bw.K > BLOCK_KMAX || e < 0 || e >= bw.K || N < 1 || B < 1) return hipErrorInvalidValue;
   BlockArgs a{U, L, N, e, J, gamma, t_end, seed, uid, step_ptr, step_offset, step_base, w, bw};
-  hipLaunchKernelGGL(cont_block_event_kernel, dim3(B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(cont_block_event_kernel<BLOCK_EVENT_THREADS>, dim3(B), dim3(BLOCK_EVENT_THREADS), 0, s, a);
   return hipGetLastError();
 }
 
