@@ -193,14 +193,14 @@ mfq_status mfq_pm_events(mfq_ctx *ctx, int32_t max_events, int32_t *counts, int3
 mfq_status mfq_ct_events(mfq_ctx *ctx, const double *gamma, uint64_t seed, int32_t n_events,
                          double t_end, int32_t reorth_every);
 
-/* Deferred events on rings (1d lattices): with block = K in 1 .. 64, mfq_ct_events keeps up to
+/* Deferred events: with block = K in 1 .. 64, mfq_ct_events keeps up to
  * K consecutive events of every trajectory in factored form -- each event taken back to the
  * block's start, where its projection is a rank-2 right factor of U plus a rank-1 term
  * (Eq. (A1) / Eq. (A2) on U) -- and applies the block with two batched matrix products and one
- * band propagation exp(-i Ht s) over the block's time s.  The events (sites, outcomes, Born
+ * band propagation exp(-i Ht s) over the block's time s (on the torus its two ring factors).  The events (sites, outcomes, Born
  * probabilities, waiting times) are those of the event-by-event form and the state agrees with
  * it to rounding.  A block is applied when full, before a scheduled Cholesky-QR and at the end
- * of every call.  block = 0 (default): event by event.  Tori always take events one by one.
+ * of every call.  block = 0 (default): event by event.
  * Needs (5 N + 3 L) K complex doubles per trajectory, allocated by the first blocked call.
  * Errors: MFQ_EINVAL (block outside 0 .. 64); the first blocked call may return MFQ_ENOMEM. */
 mfq_status mfq_set_ct_block(mfq_ctx *ctx, int32_t block);

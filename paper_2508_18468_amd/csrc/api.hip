@@ -713,7 +713,7 @@ mfq_status mfq_step(mfq_ctx *c, int32_t protocol, const double *gamma, double dt
 mfq_status ensure_blk(mfq_ctx *c) {
   const long K = c->ct_block, L = c->L, N = c->N, B = c->B;
   const size_t cpl = align_up((size_t)(5 * N * K + 3 * L * K) * B * sizeof(cplx));
-  const size_t need = cpl + (size_t)B * sizeof(double);
+  const size_t need = cpl + (size_t)B * sizeof(double) + (size_t)2 * B * sizeof(int);
   if (c->blk_cap < need) {
     if (c->blk_buf) {
       HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
@@ -734,6 +734,7 @@ mfq_status ensure_blk(mfq_ctx *c) {
   c->bw.G = p; p += L * K * B;
   c->bw.T1 = p;
   c->bw.s = reinterpret_cast<double *>(reinterpret_cast<char *>(c->blk_buf) + cpl);
+  c->bw.fb = reinterpret_cast<int *>(c->bw.s + B);
   c->bw.K = (int)K;
   HIPCHK(fill_zero(c->bw.s, (size_t)B * sizeof(double), c->stream), "block clock clear");
   return MFQ_OK;
@@ -760,15 +761,16 @@ mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t
   }
   HIPCHK(set_step(c->step_dev, c->step, false, c->stream), "step counter");
   const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
-  if (c->ct_block > 0 && c->lat.dim == 1) {  // deferred events, flushed every ct_block slots
+  if (c->ct_block > 0) {  // deferred events, flushed every ct_block slots
     mfq_status st = ensure_blk(c);
     if (st) return st;
     int e = 0;
     for (int slot = 0; slot < n_events; ++slot) {
       {
         PhaseTimer t(c, MFQ_PHASE_MEASURE);
-        HIPCHK(cont_block_event(c->X[c->cur], c->L, c->N, c->B, e, c->lat.J, c->gamma, t_end, seed, c->uid,
-                                c->step_dev, 1, c->step_base, c->ct, c->bw, c->stream), "deferred event");
+        HIPCHK(cont_block_event(c->X[c->cur], c->L, c->N, c->B, e, c->lat.dim, c->lat.Lx, Ly, c->lat.J, c->gamma,
+                                t_end, seed, c->uid, c->step_dev, 1, c->step_base, c->ct, c->bw, c->stream),
+               "deferred event");
       }
       ++e;
       HIPCHK(set_step(c->step_dev, 1, true, c->stream), "step counter");
@@ -776,12 +778,13 @@ mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t
       c->ct_any = true;
       const bool reorth = reorth_every > 0 && c->step % reorth_every == 0;
       if (e == c->ct_block || slot + 1 == n_events || reorth) {
+        bool in_b = false;
         {
           PhaseTimer t(c, MFQ_PHASE_PROPAGATE);
-          HIPCHK(cont_block_flush(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, e, c->lat.J, c->ct, c->bw,
-                                  c->stream), "deferred events flush");
+          HIPCHK(cont_block_flush(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, e, c->lat.dim, c->lat.Lx, Ly,
+                                  c->lat.J, c->ct, c->bw, &in_b, c->stream), "deferred events flush");
         }
-        c->cur = 1 - c->cur;
+        if (in_b) c->cur = 1 - c->cur;
         e = 0;
       }
       if (reorth) {

@@ -396,12 +396,11 @@ __device__ __forceinline__ void cont_apply_tile(const cplx *U, cplx *D, int L, i
 // tiles (gridDim.x of them per trajectory).
 template <bool UPDATE>
 __global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D, int L, int N, int stride,
-                                                         int period, int g_off, int band_slot, int nrb,
-                                                         int ntiles, int Lx, int Ly, int skip_lds_bands,
-                                                         ContWork w) {
+                                                         int period, int g_off, const int *bands, int bstride,
+                                                         int band_slot, int nrb, int ntiles, int Lx, int Ly,
+                                                         int skip_lds_bands, ContWork w) {
   const int b = blockIdx.y;
-  const int *info = w.info + 4 * b;
-  const int band = info[band_slot];
+  const int band = bands[bstride * b + band_slot];
   if (skip_lds_bands && ring_lds_band(band, L)) return;  // done by cont_ring_kernel
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
     cont_apply_tile<UPDATE>(U, D, L, N, stride, period, g_off, band, tile % nrb, tile / nrb, Lx, Ly, w);
@@ -414,11 +413,11 @@ __global__ __launch_bounds__(256) void cont_apply_kernel(const cplx *U, cplx *D,
 // and fixes row j / column 0 like cont_apply_kernel<true>.
 template <bool UPDATE>
 __global__ __launch_bounds__(256) void cont_ring_kernel(const cplx *U, cplx *D, int L, int N, int nrb,
-                                                        int band_slot, ContWork w) {
+                                                        const int *bands, int bstride, int band_slot, ContWork w) {
   const int b = blockIdx.y;
   const int rb = blockIdx.x % nrb, cb = blockIdx.x / nrb;
   const int *info = w.info + 4 * b;
-  const int band = info[band_slot];
+  const int band = bands[bstride * b + band_slot];
   if (!ring_lds_band(band, L)) return;
   __shared__ cplx s[RING_CT][RING_ROWS + 2 * RING_WMAX];
   __shared__ cplx gs[2 * RING_WMAX + 1];
@@ -516,7 +515,7 @@ __global__ __launch_bounds__(256) void cont_norm_kernel(cplx *U, int L, int N, C
 // G L x K.  One workgroup per trajectory; O((2w + 1) N + N e) work per event.
 struct BlockArgs {
   const cplx *U;
-  int L, N, e;
+  int L, N, e, dim, Lx, Ly;
   double J;
   const double *gamma;
   double t_end;
@@ -604,32 +603,41 @@ __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
   __syncthreads();
   const double tau = sh_tau, s_new = a.bw.s[b] + tau;
   const int j = sh_j;
-  cplx *g = a.w.g + (long)b * (L + 1);
+  const int Lx = a.Lx, Ly = a.Ly;
+  cplx *gx = a.w.g + (long)b * (Lx + Ly);
+  cplx *gy = gx + Lx;
   double *jn = a.w.jn + (long)b * a.w.jcap;
-  const int wb = ring_row_dev(2.0 * a.J * s_new, L, g, jn, a.w.jcap, &sh_w);
-  const Taps t = taps_of(wb, L);
+  const int wb = ring_row_dev(2.0 * a.J * s_new, Lx, gx, jn, a.w.jcap, &sh_w);
+  int wy = 0;
+  if (a.dim == 2) {
+    wy = ring_row_dev(2.0 * a.J * s_new, Ly, gy, jn, a.w.jcap, &sh_w);
+  } else if (tid == 0) {
+    gy[0] = cplx{1.0, 0.0};
+  }
+  __syncthreads();
+  const Taps tx = taps_of(wb, Lx), ty = taps_of(a.dim == 2 ? wy : 0, Ly);
+  const int xj = j % Lx, yj = j / Lx;
+  // sum over the band of P(s) around site j of column c (stride ld between columns)
+  auto band_row = [&](const cplx *col) -> cplx {
+    double ar = 0.0, ai = 0.0;
+    for (int dy = ty.lo; dy <= ty.hi; ++dy) {
+      const cplx gyv = gy[wrap(dy, Ly)];
+      const int row = Lx * wrap(yj - dy, Ly);
+      double sr = 0.0, si = 0.0;
+      for (int dx = tx.lo; dx <= tx.hi; ++dx) {
+        const cplx gv = gx[wrap(dx, Lx)], v = col[row + wrap(xj - dx, Lx)];
+        sr += gv.re * v.re - gv.im * v.im;
+        si += gv.re * v.im + gv.im * v.re;
+      }
+      ar += gyv.re * sr - gyv.im * si;
+      ai += gyv.re * si + gyv.im * sr;
+    }
+    return cplx{ar, ai};
+  };
   const cplx *V0 = a.U + (long)b * L * N;
   cplx *x = a.w.v + (long)b * N;  // u, then x = conj(r), then the scaled reflector
-  for (int k = tid; k < N; k += NT) {
-    const cplx *Vk = V0 + (long)k * L;
-    double ur = 0.0, ui = 0.0;
-    for (int d = t.lo; d <= t.hi; ++d) {
-      const cplx gv = g[wrap(d, L)], v = Vk[wrap(j - d, L)];
-      ur += gv.re * v.re - gv.im * v.im;
-      ui += gv.re * v.im + gv.im * v.re;
-    }
-    x[k] = cplx{ur, ui};
-  }
-  for (int f = tid; f < e; f += NT) {
-    const cplx *Gf = G + (long)f * L;
-    double gr = 0.0, gi = 0.0;
-    for (int d = t.lo; d <= t.hi; ++d) {
-      const cplx gv = g[wrap(d, L)], v = Gf[wrap(j - d, L)];
-      gr += gv.re * v.re - gv.im * v.im;
-      gi += gv.re * v.im + gv.im * v.re;
-    }
-    sh_gam[f] = cplx{gr, gi};
-  }
+  for (int k = tid; k < N; k += NT) x[k] = band_row(V0 + (long)k * L);
+  for (int f = tid; f < e; f += NT) sh_gam[f] = band_row(G + (long)f * L);
   __syncthreads();
   // q = u WL (one wave per column, lanes over rows)
   for (int c = wave; c < 2 * e; c += NW) {
@@ -769,10 +777,15 @@ __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
     }
     Zc[k + (long)e * N] = k == 0 ? cplx{sh_c.re, -sh_c.im} : cplx{0.0, 0.0};
   }
-  // g_e = P(-s) e_j: G[j + d, e] = conj(g[d]) over the band
-  for (int d = t.lo + tid; d <= t.hi; d += NT) {
-    const cplx gv = g[wrap(d, L)];
-    G[wrap(j + d, L) + (long)e * L] = cplx{gv.re, -gv.im};
+  // g_e = P(-s) e_j: G[(xj + dx, yj + dy), e] = conj(gx[dx] gy[dy]) over the band
+  {
+    const int nx = tx.hi - tx.lo + 1, ny = ty.hi - ty.lo + 1;
+    for (int q = tid; q < nx * ny; q += NT) {
+      const int dx = tx.lo + q % nx, dy = ty.lo + q / nx;
+      const cplx u = gx[wrap(dx, Lx)], v = gy[wrap(dy, Ly)];
+      const double pr = u.re * v.re - u.im * v.im, pi = u.re * v.im + u.im * v.re;
+      G[wrap(xj + dx, Lx) + Lx * wrap(yj + dy, Ly) + (long)e * L] = cplx{pr, -pi};
+    }
   }
   if (tid == 0) {
     a.bw.s[b] = s_new;
@@ -780,15 +793,22 @@ __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
   }
 }
 
-// Ring rows of P(s) for the time accumulated since the block's start (band in info[3]);
+// Ring rows of P(s) for the time accumulated since the block's start (bands in fb: x, y);
 // the block clock restarts.
-__global__ __launch_bounds__(256) void cont_block_rows_kernel(int L, double J, ContWork w, BlockWork bw) {
+__global__ __launch_bounds__(256) void cont_block_rows_kernel(int dim, int Lx, int Ly, double J, ContWork w,
+                                                              BlockWork bw) {
   const int b = blockIdx.x;
   __shared__ int sh_w;
   const double sb = bw.s[b];
-  const int wb = ring_row_dev(2.0 * J * sb, L, w.g + (long)b * (L + 1), w.jn + (long)b * w.jcap, w.jcap, &sh_w);
+  cplx *gx = w.g + (long)b * (Lx + Ly);
+  double *jn = w.jn + (long)b * w.jcap;
+  const int wx = ring_row_dev(2.0 * J * sb, Lx, gx, jn, w.jcap, &sh_w);
+  int wy = 0;
+  if (dim == 2) wy = ring_row_dev(2.0 * J * sb, Ly, gx + Lx, jn, w.jcap, &sh_w);
+  else if (threadIdx.x == 0) gx[Lx] = cplx{1.0, 0.0};
   if (threadIdx.x == 0) {
-    w.info[4 * b + 3] = wb;
+    bw.fb[2 * b] = wx;
+    bw.fb[2 * b + 1] = wy;
     bw.s[b] = 0.0;
   }
 }
@@ -832,20 +852,20 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
     // by the direct pass, whose few workgroups per trajectory exit at once otherwise
     const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
     hipLaunchKernelGGL(cont_ring_kernel<true>, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua,
-                       Ub, L, N, rnb, 2, w);
+                       Ub, L, N, rnb, (const int *)w.info, 4, 2, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 few((unsigned)std::min(ntiles, 8), B);
-    hipLaunchKernelGGL(cont_apply_kernel<true>, few, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0, 2,
-                       nrb, ntiles, Lx, Ly, 1, w);
+    hipLaunchKernelGGL(cont_apply_kernel<true>, few, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0,
+                       (const int *)w.info, 4, 2, nrb, ntiles, Lx, Ly, 1, w);
     out = Ub;
     *state_in_b = true;
   } else {
     const dim3 grid((unsigned)ntiles, B);
     hipLaunchKernelGGL(cont_apply_kernel<false>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0,
-                       2, nrb, ntiles, Lx, Ly, 0, w);
+                       (const int *)w.info, 4, 2, nrb, ntiles, Lx, Ly, 0, w);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(cont_apply_kernel<true>, grid, dim3(256), 0, s, (const cplx *)Ub, Ua, L, N, Lx, Ly, Lx,
-                       3, nrb, ntiles, Lx, Ly, 0, w);
+                       (const int *)w.info, 4, 3, nrb, ntiles, Lx, Ly, 0, w);
     out = Ua;
     *state_in_b = false;
   }
@@ -854,18 +874,20 @@ hipError_t cont_event(cplx *Ua, cplx *Ub, int L, int N, int B, int dim, int Lx, 
   return hipGetLastError();
 }
 
-hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, double J, const double *gamma,
+hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, int dim, int Lx, int Ly, double J,
+                            const double *gamma,
                             double t_end, uint64_t seed, const uint64_t *uid, const int64_t *step_ptr,
                             int step_offset, const int64_t *step_base, const ContWork &w, const BlockWork &bw,
                             hipStream_t s) {
   if (bw.K < 1 || bw.K > BLOCK_KMAX || e < 0 || e >= bw.K || N < 1 || B < 1) return hipErrorInvalidValue;
-  BlockArgs a{U, L, N, e, J, gamma, t_end, seed, uid, step_ptr, step_offset, step_base, w, bw};
+  if (L != Lx * (dim == 2 ? Ly : 1) || (dim == 1 && Ly != 1)) return hipErrorInvalidValue;
+  BlockArgs a{U, L, N, e, dim, Lx, Ly, J, gamma, t_end, seed, uid, step_ptr, step_offset, step_base, w, bw};
   hipLaunchKernelGGL(cont_block_event_kernel<BLOCK_EVENT_THREADS>, dim3(B), dim3(BLOCK_EVENT_THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, double J, const ContWork &w,
-                            const BlockWork &bw, hipStream_t s) {
+hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, int dim, int Lx, int Ly, double J,
+                            const ContWork &w, const BlockWork &bw, bool *state_in_b, hipStream_t s) {
   if (e < 1 || e > bw.K) return hipErrorInvalidValue;
   const int K = bw.K;
   hipError_t err;
@@ -900,16 +922,27 @@ hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, doub
     g.D = Ua; g.ldd = L; g.sD = (long)L * N;
     if ((err = zgemm(g, s)) != hipSuccess) return err;
   }
-  // U = P(s) V: the rows for each trajectory's time since the block's start, then the band
-  hipLaunchKernelGGL(cont_block_rows_kernel, dim3(B), dim3(256), 0, s, L, J, w, bw);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-  const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
-  hipLaunchKernelGGL(cont_ring_kernel<false>, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua, Ub,
-                     L, N, rnb, 3, w);
+  // U = P(s) V: the rows for each trajectory's time since the block's start, then the band(s)
+  hipLaunchKernelGGL(cont_block_rows_kernel, dim3(B), dim3(256), 0, s, dim, Lx, Ly, J, w, bw);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const int nrb = (L + 63) / 64, ncb = (N + 4 * CONT_CPW - 1) / (4 * CONT_CPW), ntiles = nrb * ncb;
-  hipLaunchKernelGGL(cont_apply_kernel<false>, dim3((unsigned)std::min(ntiles, 8), B), dim3(256), 0, s,
-                     (const cplx *)Ua, Ub, L, N, 1, L, 0, 3, nrb, ntiles, L, 1, 1, w);
+  if (dim == 1) {
+    const int rnb = (L + RING_ROWS - 1) / RING_ROWS, rcb = (N + RING_CT - 1) / RING_CT;
+    hipLaunchKernelGGL(cont_ring_kernel<false>, dim3((unsigned)(rnb * rcb), B), dim3(256), 0, s, (const cplx *)Ua,
+                       Ub, L, N, rnb, (const int *)bw.fb, 2, 0, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(cont_apply_kernel<false>, dim3((unsigned)std::min(ntiles, 8), B), dim3(256), 0, s,
+                       (const cplx *)Ua, Ub, L, N, 1, L, 0, (const int *)bw.fb, 2, 0, nrb, ntiles, L, 1, 1, w);
+    *state_in_b = true;
+  } else {  // P_x then P_y, back into Ua
+    const dim3 grid((unsigned)ntiles, B);
+    hipLaunchKernelGGL(cont_apply_kernel<false>, grid, dim3(256), 0, s, (const cplx *)Ua, Ub, L, N, 1, Lx, 0,
+                       (const int *)bw.fb, 2, 0, nrb, ntiles, Lx, Ly, 0, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(cont_apply_kernel<false>, grid, dim3(256), 0, s, (const cplx *)Ub, Ua, L, N, Lx, Ly, Lx,
+                       (const int *)bw.fb, 2, 1, nrb, ntiles, Lx, Ly, 0, w);
+    *state_in_b = false;
+  }
   return hipGetLastError();
 }
 

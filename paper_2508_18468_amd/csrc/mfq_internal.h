@@ -153,17 +153,19 @@ struct BlockWork {
   cplx *G;        // L x K per trajectory
   cplx *T1;       // L x 2K per trajectory (flush scratch)
   double *s;      // B: time since the block's start
+  int *fb;        // 2 per trajectory: bands of P(s) along x and y at the flush
   int K;
 };
 // Event e (0-based) of the current block for every trajectory with clock below t_end; U (the
 // state at the block's start) is only read.
-hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, double J, const double *gamma,
-                            double t_end, uint64_t seed, const uint64_t *uid, const int64_t *step_ptr,
+hipError_t cont_block_event(const cplx *U, int L, int N, int B, int e, int dim, int Lx, int Ly, double J,
+                            const double *gamma, double t_end, uint64_t seed, const uint64_t *uid, const int64_t *step_ptr,
                             int step_offset, const int64_t *step_base, const ContWork &w, const BlockWork &bw,
                             hipStream_t s);
-// Apply the block's e events: Ua (block start) is overwritten by V, Ub receives U = P(s) V.
-hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, double J, const ContWork &w,
-                            const BlockWork &bw, hipStream_t s);
+// Apply the block's e events: Ua (block start) is overwritten by V, then U = P(s) V lands in Ub
+// on the ring (*state_in_b = true) and back in Ua on the torus.
+hipError_t cont_block_flush(cplx *Ua, cplx *Ub, int L, int N, int B, int e, int dim, int Lx, int Ly, double J,
+                            const ContWork &w, const BlockWork &bw, bool *state_in_b, hipStream_t s);
 
 // ---------------------------------------------------------------- RK4 homodyne step
 // Appendix A: the homodyne step with Eq. (A4)'s exponent frozen over the step and

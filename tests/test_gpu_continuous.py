@@ -188,24 +188,27 @@ def test_full_size_ring():
     sim.close()
 
 
-@pytest.mark.parametrize("L,gammas,n_slots,K,reorth,t_end", [
-    (64, [0.3, 1.0, 2.5], 60, 1, 0, np.inf),
-    (64, [0.3, 1.0, 2.5], 60, 16, 0, np.inf),
-    (200, [0.7, 4.0], 40, 5, 8, np.inf),       # ragged tiles, Cholesky-QR inside blocks
-    (200, [0.001, 0.7], 12, 64, 0, np.inf),    # wide bands
-    (32, [0.5, 2.0], 40, 16, 0, 0.4),          # trajectories stop inside a block
+@pytest.mark.parametrize("dim,Lx,Ly,gammas,n_slots,K,reorth,t_end", [
+    (1, 64, 1, [0.3, 1.0, 2.5], 60, 1, 0, np.inf),
+    (1, 64, 1, [0.3, 1.0, 2.5], 60, 16, 0, np.inf),
+    (1, 200, 1, [0.7, 4.0], 40, 5, 8, np.inf),       # ragged tiles, Cholesky-QR inside blocks
+    (1, 200, 1, [0.001, 0.7], 12, 64, 0, np.inf),    # wide bands
+    (1, 32, 1, [0.5, 2.0], 40, 16, 0, 0.4),          # trajectories stop inside a block
+    (2, 8, 6, [0.3, 1.5], 40, 16, 0, np.inf),        # torus: full rows along both directions
+    (2, 96, 2, [0.05, 2.0], 30, 7, 9, np.inf),       # torus: band along x, Ly = 2, ragged tiles
+    (2, 6, 6, [0.5, 1.0], 24, 8, 0, 0.5),            # torus: trajectories stop inside a block
 ])
-def test_deferred_events_equal_event_by_event_and_oracle(L, gammas, n_slots, K, reorth, t_end):
+def test_deferred_events_equal_event_by_event_and_oracle(dim, Lx, Ly, gammas, n_slots, K, reorth, t_end):
     """Blocks of K deferred events (one call of n_slots slots) against the same slots taken one
     by one and against the oracle: same last events, same clocks, C to 2e-11."""
     B, seed = len(gammas), 23
     uids = [4 + 3 * b for b in range(B)]
-    blk = make_sim(1, L, n_traj=B, uids=uids)
-    one = make_sim(1, L, n_traj=B, uids=uids)
+    blk = make_sim(dim, Lx, Ly, n_traj=B, uids=uids)
+    one = make_sim(dim, Lx, Ly, n_traj=B, uids=uids)
     blk.set_ct_block(K)
     blk.ct_events(gammas, seed, n_slots, t_end=t_end, reorth_every=reorth)
     one.ct_events(gammas, seed, n_slots, t_end=t_end, reorth_every=reorth)
-    orc = OracleCT(1, L, 1, uids, gammas, seed)
+    orc = OracleCT(dim, Lx, Ly, uids, gammas, seed)
     for _ in range(n_slots):
         recs = orc.slot(t_end)
     _check_slot(blk, orc, recs)
