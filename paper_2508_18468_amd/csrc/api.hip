@@ -489,10 +489,9 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
   }
   {
     PhaseTimer t(c, MFQ_PHASE_REORTH);
-    HIPCHK(cholqr_pass(Xb, Xa, L, N, B, c->chol, false, c->stream), "cholqr pass 1");
-    HIPCHK(cholqr_pass(Xa, Xb, L, N, B, c->chol, true, c->stream), "cholqr pass 2");
+    HIPCHK(cholqr2(Xb, Xa, L, N, B, c->chol, c->stream), "cholqr2");
   }
-  c->cur = pidx;
+  c->cur = 1 - pidx;  // the orthonormal factor is in Xa
   return MFQ_OK;
 }
 
@@ -789,10 +788,8 @@ mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t
       }
       if (reorth) {
         PhaseTimer t(c, MFQ_PHASE_REORTH);
-        HIPCHK(cholqr_pass(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, false, c->stream),
-               "cholqr pass 1");
-        HIPCHK(cholqr_pass(c->X[1 - c->cur], c->X[c->cur], c->L, c->N, c->B, c->chol, true, c->stream),
-               "cholqr pass 2");
+        HIPCHK(cholqr2(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, c->stream), "cholqr2");
+        c->cur = 1 - c->cur;
       }
     }
     return MFQ_OK;
@@ -811,10 +808,8 @@ mfq_status mfq_ct_events(mfq_ctx *c, const double *gamma, uint64_t seed, int32_t
     c->ct_any = true;
     if (reorth_every > 0 && c->step % reorth_every == 0) {
       PhaseTimer t(c, MFQ_PHASE_REORTH);
-      HIPCHK(cholqr_pass(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, false, c->stream),
-             "cholqr pass 1");
-      HIPCHK(cholqr_pass(c->X[1 - c->cur], c->X[c->cur], c->L, c->N, c->B, c->chol, true, c->stream),
-             "cholqr pass 2");
+      HIPCHK(cholqr2(c->X[c->cur], c->X[1 - c->cur], c->L, c->N, c->B, c->chol, c->stream), "cholqr2");
+      c->cur = 1 - c->cur;
     }
   }
   return MFQ_OK;

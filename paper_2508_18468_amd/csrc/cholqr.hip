@@ -8,8 +8,9 @@
 // inverse R^{-1} assembled block column by block column from GEMMs, and the
 // triangular product U R^{-1} (zero blocks of R^{-1} skipped).  Two passes
 // (Cholesky-QR2) bring U^+ U to identity at working precision for the
-// condition numbers a step produces; the second pass keeps U as it is when its
-// Gram certifies |U^+ U - I| <= CHOL_KEEP_MAX entrywise.
+// condition numbers a step produces; the second pass keeps the first pass's
+// result in place when its Gram certifies |U^+ U - I| <= CHOL_KEEP_MAX entrywise,
+// so that, as in every step of the workloads here, it costs one Gram and no copy.
 #include "mfq_internal.h"
 
 namespace mfq {
@@ -110,6 +111,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
   if (tid == 0 && bad) atomicOr(flag, 1);
 }
 
+// Pass 2 did not certify its input (max |G - I| above thr or not finite): its product,
+// formed in src, becomes the result in dst.  Otherwise every workgroup exits at once.
+__global__ __launch_bounds__(256) void keep_or_copy_kernel(const double2 *src, double2 *dst, long n,
+                                                           const double *dev, double thr) {
+  if (*dev <= thr) return;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) dst[i] = src[i];
+}
+
 GemmDesc desc() {
   GemmDesc g{};
   g.alpha = cplx{1.0, 0.0};
@@ -117,8 +126,8 @@ GemmDesc desc() {
   return g;
 }
 
-}  // namespace
-
+// One pass: Uout = Uin R^{-1}.  near_identity (pass 2): Uout is not written when the Gram
+// certifies Uin (max |G - I| <= CHOL_KEEP_MAX, left in wk.dev).
 hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &wk,
                        bool near_identity, hipStream_t s) {
   hipError_t e;
@@ -215,8 +224,8 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
       }
     }
   }
-  // Uout = Uin R^{-1}; in the second pass a copy when Uin is already orthonormal to
-  // CHOL_KEEP_MAX (decided on the device from the Gram's max |G - I|)
+  // Uout = Uin R^{-1}; in the second pass skipped on the device when Uin is already
+  // orthonormal to CHOL_KEEP_MAX
   {
     GemmDesc g = desc();
     g.M = L; g.N = N; g.K = N; g.batch = B;
@@ -224,12 +233,26 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
     g.B = wk.Rinv; g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;
     g.D = Uout; g.ldd = L; g.sD = (long)L * N;
     if (near_identity) {
-      g.copy_if_le = wk.dev;
-      g.copy_thr = CHOL_KEEP_MAX;
+      g.skip_if_le = wk.dev;
+      g.skip_thr = CHOL_KEEP_MAX;
     }
     if ((e = zgemm(g, s)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t cholqr2(cplx *U, cplx *T, int L, int N, int B, const CholWork &wk, hipStream_t s) {
+  if (U == T) return hipErrorInvalidValue;
+  hipError_t e = cholqr_pass(U, T, L, N, B, wk, false, s);
+  if (e != hipSuccess) return e;
+  if ((e = cholqr_pass(T, U, L, N, B, wk, true, s)) != hipSuccess) return e;
+  const long n = (long)L * N * B;
+  const unsigned blocks = (unsigned)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(keep_or_copy_kernel, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2 *>(U),
+                     reinterpret_cast<double2 *>(T), n, (const double *)wk.dev, CHOL_KEEP_MAX);
+  return hipGetLastError();
 }
 
 }  // namespace mfq

@@ -41,10 +41,6 @@ struct GemmDesc {
   // stores per tile the sums of |D_ij|^2 (i < j) along each diagonal j - i, a general one
   // stores per tile the sum of |D_ij|^2 (see zgemm_partials, zgemm_ring_bins, zgemm_tile_sum).
   double *part;
-  // Certified skip of a triangular product U R^{-1} with R^{-1} = I + O(E) (op N x op N,
-  // square B, bUpper): if *copy_if_le <= copy_thr, D = A is copied instead.
-  const double *copy_if_le;
-  double copy_thr;
   // Two batch dimensions: with batch2 > 1, entry b of the batch is (b / batch2, b % batch2)
   // and its operands sit at X + (b / batch2) sX + (b % batch2) sX2 (batch2 <= 1: X + b sX).
   int batch2;
@@ -192,13 +188,13 @@ constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
 // already delivered an orthonormal basis to that accuracy, which the second pass's own
 // rounding (about L eps per entry of the Gram) would not improve on.
 constexpr double CHOL_KEEP_MAX = 1e-13;
-// One Cholesky-QR pass: Uout = Uin * R^{-1}, R = chol(Uin^+ Uin).  With
-// near_identity, the Gram is first tested against I: if every entry of
-// E = G - I is below CHOL_FIRST_ORDER_MAX, R^{-1} = I - triu(E) + diag(E)/2 (the
-// Cholesky factor of I + E to O(|E|^2), i.e. to rounding); otherwise the full
-// factorisation runs.  The choice is made on the device.
-hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &w,
-                       bool near_identity, hipStream_t s);
+// Cholesky-QR2 of the L x N matrices U (batch B): the orthonormal factor ends in T, and U
+// is overwritten (scratch).  Pass 1: T = U R^{-1}, R = chol(U^+ U).  Pass 2 tests the Gram
+// of T against I on the device: max |G - I| <= CHOL_KEEP_MAX keeps T as it is (the pass's
+// launches exit at once); otherwise R^{-1} = I - triu(E) + diag(E)/2 for E = G - I below
+// CHOL_FIRST_ORDER_MAX (the Cholesky factor of I + E to O(|E|^2), i.e. to rounding), else
+// the full factorisation, and T R^{-1} is formed in U and copied back into T.
+hipError_t cholqr2(cplx *U, cplx *T, int L, int N, int B, const CholWork &w, hipStream_t s);
 
 // ---------------------------------------------------------------- fused small-lattice path
 struct FusedArgs {

@@ -75,8 +75,7 @@ __device__ inline void upper_tile(int t, int &tm, int &tn) {
 enum { FL_MASK = 1,      // triangular operands (aUpper / bUpper) masked at load
        FL_NEAR_ID = 2,   // near-identity epilogue (R1, maxdev)
        FL_SQSUM = 4,     // per-tile sum of |D_ij|^2 into part (D not written)
-       FL_DIAG = 8,      // per-tile sums of |D_ij|^2, i < j, along each diagonal (D not written)
-       FL_COPYSKIP = 16 };  // D = A instead of the product when *copy_if_le <= copy_thr
+       FL_DIAG = 8 };    // per-tile sums of |D_ij|^2, i < j, along each diagonal (D not written)
 
 // Reduction epilogues.  scratch: the A-plane LDS of the tile (2 KT (MT + 1) doubles), free
 // once the K loop is over.  Every sum runs in a fixed order, so results are reproducible.
@@ -195,17 +194,6 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   }
   const int m0 = tm * MT, n0 = tn * NT;
   if (g.tri == TRI_UPPER && m0 > n0 + NT - 1) return;  // tile entirely below the diagonal
-  if constexpr ((FL & FL_COPYSKIP) != 0) {
-    if (*g.copy_if_le <= g.copy_thr) {  // the factor is the identity to the accuracy kept
-      const cplx *Ab = g.A + batch_offset(g, b, g.sA, g.sA2);
-      cplx *Db = g.D + batch_offset(g, b, g.sD, g.sD2);
-      for (int e = threadIdx.x; e < MT * NT; e += blockDim.x) {
-        const int row = m0 + e % MT, col = n0 + e / MT;
-        if (row < g.M && col < g.N) Db[row + (long)col * g.ldd] = Ab[row + (long)col * g.lda];
-      }
-      return;
-    }
-  }
   int kbeg = 0, kend = g.K;
   if (g.aUpper) kbeg = (m0 / KT) * KT;
   if (g.bUpper) kend = min(g.K, n0 + NT);
@@ -473,12 +461,6 @@ hipError_t launch(const GemmDesc &g, hipStream_t s) {
                             dim3(nthreads<NT>()), 0, s, g);
   } else if (g.idxA || g.idxB) {
     launch_ops<MT, NT, true, true>(g, grid, s);
-  } else if (g.copy_if_le) {
-    if (g.opA != OP_N || g.opB != OP_N || g.K != g.N || g.idxA || g.idxB) return hipErrorInvalidValue;
-    if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N, MT, NT, false, true, FL_MASK | FL_COPYSKIP>), grid,
-                                 block, 0, s, g);
-    else hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_N, MT, NT, false, false, FL_MASK | FL_COPYSKIP>), grid,
-                            block, 0, s, g);
   } else if (g.aUpper || g.bUpper) {
     if (edge) launch_ops<MT, NT, false, true, FL_MASK>(g, grid, s);
     else launch_ops<MT, NT, false, false, FL_MASK>(g, grid, s);
