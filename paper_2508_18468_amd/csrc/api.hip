@@ -187,7 +187,9 @@ void carve(Plan &pl, const mfq_lattice &lat, int L, int N, int B, int precision,
   c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
   c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
   c->step_base = step_base;
-  c->eig = EigWork{G, ev, ew, ep, etau, ed, ee, elam, eS};
+  // the blocked reduction keeps its panels in Rinv (free outside a step; 4 TRD_NB n <= N^2 for
+  // n >= TRD_BLOCKED_MIN)
+  c->eig = EigWork{G, ev, ew, ep, etau, ed, ee, elam, eS, Rinv, (long)NN};
   c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
   c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
   c->pm_v = pm_v; c->pm_w = pm_w;

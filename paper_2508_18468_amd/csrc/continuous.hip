@@ -536,33 +536,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 constexpr int BLOCK_KMAX = 64;
 constexpr int BLOCK_EVENT_THREADS = 1024;
 
-// Sum / max over the NT threads of a workgroup (wave shuffles, then the wave partials in a
-// fixed order); every thread receives the result.
-template <int NT>
-__device__ __forceinline__ double block_sum_nt(double v, double *red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < NT / 64; ++q) s += red[q];
-  return s;
-}
-template <int NT>
-__device__ __forceinline__ double block_max_nt(double v, double *red) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double m = 0.0;
-#pragma unroll
-  for (int q = 0; q < NT / 64; ++q) m = fmax(m, red[q]);
-  return m;
-}
-
 template <int NT>
 __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
   constexpr int NW = NT / 64;

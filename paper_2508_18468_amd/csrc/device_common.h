@@ -28,6 +28,33 @@ __device__ __forceinline__ double block_max256(double v, double *red) {
   return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+// Sum / maximum over the NT threads of a workgroup (wave shuffles, then the wave partials in
+// a fixed order); every thread receives the result.  red: NT / 64 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ double block_sum_nt(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) s += red[q];
+  return s;
+}
+template <int NT>
+__device__ __forceinline__ double block_max_nt(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double m = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) m = fmax(m, red[q]);
+  return m;
+}
+
 // Vectors whose largest component is below this are treated as zero when a
 // reflector is formed (dropping them changes the result by less than that).
 constexpr double REFLECT_TINY = 1e-290;

@@ -18,10 +18,15 @@
 //                update A -= v w^+ + w v^+ of reflector k-1 to column j and
 //                forms p_j = sum_i conj(A_ij) v_k,i, i.e. (A v_k)_j for
 //                Hermitian A.
-// Every sweep reads and writes the trailing matrix once (HBM-bound).
+// Every sweep reads and writes the trailing matrix once (HBM-bound).  Batches
+// with enough work take the blocked form below instead (panels of TRD_NB
+// reflectors, the trailing matrix only read per reflector and written once per
+// panel by a GEMM), which halves that traffic.
 // Bisection: one lane per eigenvalue when the batch offers enough of them,
 // otherwise one wave per eigenvalue that splits its interval at 64 points per
 // Sturm pass (65-fold narrowing per pass instead of 2-fold).
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace mfq {
@@ -193,6 +198,287 @@ __global__ __launch_bounds__(256) void tri_sweep_kernel(EigWork W, int n, int k)
   }
 }
 
+// ---------------------------------------------------------------- blocked reduction
+// Matrices of n >= TRD_BLOCKED_MIN are reduced in panels of TRD_NB columns.  Within a panel
+// the trailing matrix is not written: A_cur = A - sum_t (v_t w_t^+ + w_t v_t^+) over the
+// panel's earlier reflectors t, so that
+//   A_cur v = A v - sum_t (v_t (w_t^+ v) + w_t (v_t^+ v))
+// reads the trailing matrix once, read-only, and column k is corrected only when it is
+// reduced.  At the end of the panel the trailing matrix takes all of the panel's reflectors in
+// one GEMM, A -= [V W] [W V]^+, on the matrix cores; the last LDS_MAX_N columns are reduced in
+// LDS.  For reflector r of a panel (column k0 + r) three launches:
+//   trd_hemv(r)    grid: y_c = sum_i conj(A_ic) v_i over columns c > k0 + r (one wave per
+//                  group of columns), and, in the first TRD_ZCH workgroups, partial sums over
+//                  row chunks of z = (W^+ v, V^+ v) against the panel's earlier reflectors;
+//   trd_panel(r+1) grid over rows i >= k = k0 + r + 1: y_i corrected by the panel,
+//                  partial sums of v^+ y, and column k corrected by the panel except for the
+//                  part of reflector r's w that needs v^+ y;
+//   trd_reflect(r+1) one workgroup per matrix: w_r = tau y - (tau^2/2)(v^+ y) v, the rest of
+//                  column k, d_k and reflector r + 1 of column k.
+// Every pass over the panel runs grid-wide; the one-workgroup step is O(n).  Panel storage per
+// matrix (ld n): X = [V W] (v_t in column t, w_t in column jp + t), Y = [W V] at column offset
+// 2 TRD_NB, then the z and v^+ y partial sums.  The corrected y goes to the first n entries of
+// the reflector slots v (the hemv output y stays in p).
+constexpr int TRD_REFLECT_THREADS = 1024;
+constexpr int TRD_ZCH = 16;        // row chunks of the z partial sums
+constexpr int TRD_PANEL_ROWS = 256;
+static_assert(TRD_ZCH == 16 && TRD_PANEL_ROWS == 256, "trd_panel_elems sizes the panel storage for these");
+
+__device__ __forceinline__ cplx cmul_conj_a(cplx a, cplx x) {  // conj(a) x
+  return cplx{a.re * x.re + a.im * x.im, a.re * x.im - a.im * x.re};
+}
+__device__ __forceinline__ cplx cmul(cplx a, cplx x) {
+  return cplx{a.re * x.re - a.im * x.im, a.re * x.im + a.im * x.re};
+}
+
+struct PanelPtrs {
+  cplx *X, *Y, *zpart, *kpart;
+};
+__device__ __forceinline__ PanelPtrs panel_ptrs(const EigWork &W, int b, int n) {
+  PanelPtrs q;
+  q.X = W.panel + (long)b * W.panel_stride;
+  q.Y = q.X + (long)2 * TRD_NB * n;
+  q.zpart = q.Y + (long)2 * TRD_NB * n;
+  q.kpart = q.zpart + TRD_ZCH * 2 * TRD_NB;
+  return q;
+}
+
+// y_raw = A v_r over columns c > k0 + r; z partial sums over row chunks (workgroups < TRD_ZCH).
+template <int CPW>
+__global__ __launch_bounds__(256) void trd_hemv_kernel(EigWork W, int n, int k0, int jp, int r) {
+  const int b = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = k0 + r;
+  if (W.tau[2 * b + (k & 1)] == 0.0) return;
+  const PanelPtrs q = panel_ptrs(W, b, n);
+  const cplx *v = q.X + (long)r * n;
+  if (blockIdx.x < TRD_ZCH && r > 0) {  // z_t = w_t^+ v, z_{r+t} = v_t^+ v over this row chunk
+    const int rows = n - k - 1, csz = (rows + TRD_ZCH - 1) / TRD_ZCH;
+    const int i0 = k + 1 + blockIdx.x * csz, i1 = min(n, i0 + csz);
+    for (int t2 = wave; t2 < 2 * r; t2 += 4) {
+      const cplx *c = q.X + (long)(t2 < r ? jp + t2 : t2 - r) * n;
+      double zr = 0.0, zi = 0.0;
+      for (int i = i0 + lane; i < i1; i += 64) {
+        const cplx x = cmul_conj_a(c[i], v[i]);
+        zr += x.re;
+        zi += x.im;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        zr += __shfl_down(zr, o, 64);
+        zi += __shfl_down(zi, o, 64);
+      }
+      if (lane == 0) q.zpart[blockIdx.x * 2 * TRD_NB + t2] = cplx{zr, zi};
+    }
+  }
+  const int c0 = k + 1 + (blockIdx.x * 4 + wave) * CPW;
+  if (c0 >= n) return;
+  const cplx *A = W.A + (long)b * n * n;
+  cplx *y = W.p + (long)b * n;
+  double pr[CPW], pim[CPW];
+  int jc[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    jc[c] = min(c0 + c, n - 1);  // columns past the end repeat the last one, unwritten
+    pr[c] = pim[c] = 0.0;
+  }
+  for (int i = k + 1 + lane; i < n; i += 64) {
+    const cplx xv = v[i];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const cplx x = cmul_conj_a(A[i + (long)jc[c] * n], xv);
+      pr[c] += x.re;
+      pim[c] += x.im;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    double sr = pr[c], si = pim[c];
+    for (int o = 32; o > 0; o >>= 1) {
+      sr += __shfl_down(sr, o, 64);
+      si += __shfl_down(si, o, 64);
+    }
+    if (lane == 0 && c0 + c < n) y[c0 + c] = cplx{sr, si};
+  }
+}
+
+// Rows i >= k = k0 + r + 1 of matrix blockIdx.y (TRD_PANEL_ROWS per workgroup), for reflector r:
+//   y_i = y_raw_i - sum_{t<r} (v_t[i] z_t + w_t[i] z_{r+t})      (into W.v)
+//   partial sum of conj(v_r[i]) y_i                             (into kpart)
+//   with_col: a_i = A_ik - sum_{t<r} (v_t[i] conj(w_t[k]) + w_t[i] conj(v_t[k]))
+//                        - tau_r (v_r[i] conj(y_k) + y_i conj(v_r[k]))   (into column k)
+__global__ __launch_bounds__(TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, int n, int k0, int jp, int r,
+                                                                   int with_col) {
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int k = k0 + r + 1;
+  const int i = k + blockIdx.x * TRD_PANEL_ROWS + tid;
+  const PanelPtrs q = panel_ptrs(W, b, n);
+  const double tp = W.tau[2 * b + ((k - 1) & 1)];
+  __shared__ cplx zs[2 * TRD_NB], rowk[2 * TRD_NB];
+  __shared__ double red[TRD_PANEL_ROWS / 64];
+  __shared__ cplx sh_yk;
+  if (tp != 0.0)
+    for (int t2 = tid; t2 < 2 * r; t2 += TRD_PANEL_ROWS) {  // z summed over the row chunks in order
+      cplx acc{0.0, 0.0};
+      for (int c = 0; c < TRD_ZCH; ++c) {
+        const cplx x = q.zpart[c * 2 * TRD_NB + t2];
+        acc.re += x.re;
+        acc.im += x.im;
+      }
+      zs[t2] = acc;
+    }
+  if (with_col)
+    for (int t2 = tid; t2 < 2 * r; t2 += TRD_PANEL_ROWS)  // v_t[k], w_t[k]
+      rowk[t2] = q.X[k + (long)(t2 < r ? t2 : jp + t2 - r) * n];
+  __syncthreads();
+  const cplx *yraw = W.p + (long)b * n;
+  cplx *ycor = W.v + (long)b * 2 * n;
+  auto y_at = [&](int row) {
+    cplx yv = yraw[row];
+    for (int t = 0; t < r; ++t) {
+      const cplx a = cmul(q.X[row + (long)t * n], zs[t]), c = cmul(q.X[row + (long)(jp + t) * n], zs[r + t]);
+      yv.re -= a.re + c.re;
+      yv.im -= a.im + c.im;
+    }
+    return yv;
+  };
+  if (tid == 0) sh_yk = tp != 0.0 ? y_at(k) : cplx{0.0, 0.0};
+  __syncthreads();
+  const cplx *vr = q.X + (long)r * n;
+  double kr = 0.0, ki = 0.0;
+  if (i < n) {
+    cplx yi{0.0, 0.0};
+    if (tp != 0.0) {
+      yi = y_at(i);
+      ycor[i] = yi;
+      const cplx x = cmul_conj_a(vr[i], yi);
+      kr = x.re;
+      ki = x.im;
+    }
+    if (with_col) {
+      cplx *col = W.A + (long)b * n * n + (long)k * n;
+      cplx a = col[i];
+      for (int t = 0; t < r; ++t) {
+        const cplx vi = q.X[i + (long)t * n], wi = q.X[i + (long)(jp + t) * n];
+        const cplx vk = rowk[t], wk = rowk[r + t];
+        a.re -= (vi.re * wk.re + vi.im * wk.im) + (wi.re * vk.re + wi.im * vk.im);
+        a.im -= (vi.im * wk.re - vi.re * wk.im) + (wi.im * vk.re - wi.re * vk.im);
+      }
+      if (tp != 0.0) {  // - tau (v_r[i] conj(y_k) + y_i conj(v_r[k]))
+        const cplx vi = vr[i], vk = vr[k], yk = sh_yk;
+        a.re -= tp * ((vi.re * yk.re + vi.im * yk.im) + (yi.re * vk.re + yi.im * vk.im));
+        a.im -= tp * ((vi.im * yk.re - vi.re * yk.im) + (yi.im * vk.re - yi.re * vk.im));
+      }
+      col[i] = a;
+    }
+  }
+  kr = block_sum_nt<TRD_PANEL_ROWS>(kr, red);
+  ki = block_sum_nt<TRD_PANEL_ROWS>(ki, red);
+  if (tid == 0) q.kpart[blockIdx.x] = cplx{kr, ki};
+}
+
+// One workgroup per matrix: for r = j - 1 >= 0, K = (tau^2/2) v_r^+ y and w_r = tau y - K v_r
+// (rows >= k = k0 + j), and the last part of column k's correction, 2 Re(K) v_r[i] conj(v_r[k]);
+// for j < jp, d_k and reflector j of column k.
+template <int NT>
+__global__ __launch_bounds__(NT) void trd_reflect_kernel(EigWork W, int n, int k0, int jp, int j) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int k = k0 + j;
+  const PanelPtrs q = panel_ptrs(W, b, n);
+  double *d = W.d + (long)b * n, *e = W.e + (long)b * n;
+  __shared__ double red[NT / 64];
+  __shared__ double sh_dk, sh_tau;
+  __shared__ cplx sh_x0;
+  cplx *col = W.A + (long)b * n * n + (long)k * n;
+  double two_kr = 0.0;
+  const cplx *vr = q.X + (long)(j > 0 ? j - 1 : 0) * n;
+  if (j >= 1) {
+    const int r = j - 1;
+    const double tp = W.tau[2 * b + ((k - 1) & 1)];
+    cplx K{0.0, 0.0};
+    if (tp != 0.0) {
+      const int nch = (n - k + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS;
+      for (int c = 0; c < nch; ++c) {  // fixed order
+        K.re += q.kpart[c].re;
+        K.im += q.kpart[c].im;
+      }
+      K.re *= 0.5 * tp * tp;
+      K.im *= 0.5 * tp * tp;
+    }
+    two_kr = 2.0 * K.re;
+    const cplx *y = W.v + (long)b * 2 * n;
+    cplx *wx = q.X + (long)(jp + r) * n, *wy = q.Y + (long)r * n;
+    for (int i = k + tid; i < n; i += NT) {
+      cplx wi{0.0, 0.0};
+      if (tp != 0.0) {
+        const cplx vi = vr[i], yi = y[i];
+        wi = cplx{tp * yi.re - (K.re * vi.re - K.im * vi.im), tp * yi.im - (K.re * vi.im + K.im * vi.re)};
+      }
+      wx[i] = wi;
+      wy[i] = wi;
+    }
+  }
+  if (j == jp) return;  // the panel's last w only
+  const cplx vrk = j >= 1 ? vr[k] : cplx{0.0, 0.0};
+  double mx = 0.0;
+  for (int i = k + tid; i < n; i += NT) {
+    cplx a = col[i];
+    if (j >= 1 && two_kr != 0.0) {  // + 2 Re(K) v_r[i] conj(v_r[k])
+      const cplx x = cmul_conj_a(vrk, vr[i]);
+      a.re += two_kr * x.re;
+      a.im += two_kr * x.im;
+      col[i] = a;
+    }
+    if (i == k) sh_dk = a.re;
+    else mx = fmax(mx, cmax_abs(a));
+    if (i == k + 1) sh_x0 = a;
+  }
+  // reflector of rows k+1 .. n-1, formed from the column scaled by its largest component
+  const double s = block_max_nt<NT>(mx, red);
+  const double inv = s >= REFLECT_TINY ? 1.0 / s : 0.0;
+  cplx *vk = q.X + (long)j * n, *vy = q.Y + (long)(jp + j) * n;
+  double part = 0.0;
+  for (int i = k + tid; i < n; i += NT) {  // each thread rereads the entries it wrote
+    if (i < k + 2) continue;
+    const cplx a{col[i].re * inv, col[i].im * inv};
+    part += a.re * a.re + a.im * a.im;
+    vk[i] = a;
+  }
+  const double tail2 = block_sum_nt<NT>(part, red);  // its barriers publish sh_dk, sh_x0
+  if (tid == 0) {
+    d[k] = sh_dk;
+    const cplx x0 = sh_x0;
+    double tau = 0.0;
+    if (tail2 == 0.0) {  // nothing below x0 (or all below REFLECT_TINY): H = I
+      e[k] = hypot(x0.re, x0.im);
+    } else {
+      const Reflector h = make_reflector(cplx{x0.re * inv, x0.im * inv}, tail2, s);
+      vk[k + 1] = h.v0;
+      e[k] = h.norm;
+      tau = h.tau;
+    }
+    W.tau[2 * b + (k & 1)] = tau;
+    sh_tau = tau;
+  }
+  __syncthreads();
+  const bool zero = sh_tau == 0.0;  // H = I: a zero column, so that its w and corrections vanish
+  for (int i = k + 1 + tid; i < n; i += NT) {
+    if (zero) vk[i] = cplx{0.0, 0.0};
+    vy[i] = vk[i];
+  }
+}
+
+// The trailing block from column k0 on (at most LDS_MAX_N) reduced in LDS: d[k0 ..],
+// e[k0 ..].
+__global__ __launch_bounds__(256) void trd_tail_kernel(EigWork w, int n, int k0) {
+  const int b = blockIdx.x, m = n - k0;
+  __shared__ cplx As[LDS_MAX_N * LDS_MAX_N];
+  __shared__ cplx vs[LDS_MAX_N], ps[LDS_MAX_N];
+  __shared__ double red[4];
+  const cplx *Ab = w.A + (long)b * n * n + (long)k0 * (n + 1);
+  for (int q = threadIdx.x; q < m * m; q += 256) As[q] = Ab[q % m + (long)(q / m) * n];
+  __syncthreads();
+  tridiag_body(As, m, m, vs, ps, w.d + (long)b * n + k0, w.e + (long)b * n + k0, red);
+}
+
 // Eigenvalue k (ascending) of tridiagonal b (see bisect_eigenvalue).
 __global__ __launch_bounds__(256) void bisect_kernel(EigWork w, int n) {
   const int b = blockIdx.y;
@@ -275,11 +561,62 @@ hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, in
   return zgemm(g, s);
 }
 
+namespace {
+
+hipError_t tridiagonalize_blocked(const EigWork &w, int n, int B, hipStream_t s) {
+  const int kstop = n - LDS_MAX_N;  // columns reduced in panels; the rest in LDS
+  hipError_t err;
+  const dim3 one(B), rt(TRD_REFLECT_THREADS);
+  for (int k0 = 0; k0 < kstop; k0 += TRD_NB) {
+    const int jp = std::min(TRD_NB, kstop - k0);
+    for (int j = 0; j <= jp; ++j) {
+      if (j >= 1) {  // y of reflector j - 1 and column k0 + j corrected by the panel
+        const int rows = n - (k0 + j);
+        hipLaunchKernelGGL(trd_panel_kernel, dim3((unsigned)((rows + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS), B),
+                           dim3(TRD_PANEL_ROWS), 0, s, w, n, k0, jp, j - 1, j < jp ? 1 : 0);
+      }
+      hipLaunchKernelGGL(trd_reflect_kernel<TRD_REFLECT_THREADS>, one, rt, 0, s, w, n, k0, jp, j);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+      if (j == jp) break;
+      const long m = n - (k0 + j) - 1;
+      long gx;
+      if ((gx = (m + 15) / 16) * B >= 512)
+        hipLaunchKernelGGL(trd_hemv_kernel<4>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0, s,
+                           w, n, k0, jp, j);
+      else if ((gx = (m + 7) / 8) * B >= 512)
+        hipLaunchKernelGGL(trd_hemv_kernel<2>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0, s,
+                           w, n, k0, jp, j);
+      else
+        hipLaunchKernelGGL(trd_hemv_kernel<1>, dim3((unsigned)std::max<long>((m + 3) / 4, TRD_ZCH), B),
+                           dim3(256), 0, s, w, n, k0, jp, j);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    // A22 -= [V W] [W V]^+ over the trailing block
+    const int k1 = k0 + jp, m = n - k1;
+    GemmDesc g{};
+    g.alpha = cplx{-1.0, 0.0};
+    g.beta = cplx{1.0, 0.0};
+    g.M = m; g.N = m; g.K = 2 * jp; g.batch = B;
+    g.A = w.panel + k1; g.lda = n; g.sA = w.panel_stride; g.opA = OP_N;
+    g.B = w.panel + (long)2 * TRD_NB * n + k1; g.ldb = n; g.sB = w.panel_stride; g.opB = OP_C;
+    g.Cin = w.A + (long)k1 * (n + 1); g.ldcin = n; g.sCin = (long)n * n;
+    g.D = w.A + (long)k1 * (n + 1); g.ldd = n; g.sD = (long)n * n;
+    if ((err = zgemm(g, s)) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(trd_tail_kernel, dim3(B), dim3(256), 0, s, w, n, kstop);
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s) {
   if (n <= LDS_MAX_N) {
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(B), dim3(256), 0, s, w, n);
     return hipGetLastError();
   }
+  if (n >= TRD_BLOCKED_MIN && (double)n * n * B >= TRD_BLOCKED_WORK && w.panel &&
+      w.panel_stride >= trd_panel_elems(n))
+    return tridiagonalize_blocked(w, n, B, s);
   for (int k = 0; k <= n - 2; ++k) {
     hipLaunchKernelGGL(tri_col_kernel, dim3(B), dim3(256), 0, s, w, n, k);
     if (k == n - 2) break;

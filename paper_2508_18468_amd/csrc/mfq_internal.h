@@ -240,7 +240,18 @@ struct EigWork {
   cplx *p;      // n per trajectory: A v of the newest reflector
   double *tau;  // 2 per trajectory: tau of the two reflector slots
   double *d, *e, *lam, *S;
+  cplx *panel;        // blocked reduction: panel factors and partial sums (trd_panel_elems(n))
+  long panel_stride;  // between trajectories
 };
+// Panel width of the blocked Householder reduction, which takes batches of n >= TRD_BLOCKED_MIN
+// with B n^2 >= TRD_BLOCKED_WORK (below that the per-reflector sweep, with fewer launches per
+// column, is faster: launch latency rather than HBM traffic bounds the reduction there).
+constexpr int TRD_NB = 32;
+constexpr int TRD_BLOCKED_MIN = 512;
+constexpr double TRD_BLOCKED_WORK = 16777216.0;
+// Complex entries of the blocked reduction's per-matrix storage: X and Y (n x 2 TRD_NB each),
+// 16 row chunks of z partial sums (2 TRD_NB each) and one v^+ y partial per 256 rows.
+inline long trd_panel_elems(int n) { return (long)4 * TRD_NB * n + 16L * 2 * TRD_NB + (n + 255) / 256; }
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,
                        int *n_out, hipStream_t s);
 hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s);

@@ -176,3 +176,48 @@ def test_known_spectrum_with_tiny_couplings(half):
         err = float(np.max(np.abs(got - np.sort(lam))))
         assert err <= 200 * len(region) * EPS, (eps, err)
     sim.close()
+
+
+def test_known_spectrum_blocked_reduction():
+    """40 trajectories, L=1300, N=650, a random region of 650 sites: enough work for the
+    blocked reduction (panels of 32 reflectors, the last panel ragged, then the 88-column block
+    in LDS); every trajectory's spectrum and entropy against its known spectrum."""
+    L, N, B, l = 1300, 650, 40, 650
+    rng = np.random.default_rng(41)
+    region = sorted(rng.choice(L, l, replace=False).tolist())
+    lams = [spectrum_mix(l, rng) for _ in range(B)]
+    U = np.concatenate([known_state(L, N, region, lam, rng) for lam in lams])
+    sim = make_sim(1, L, n_traj=B)
+    sim.set_state(U, 0)
+    got = sim.region_spectrum(region)
+    S = sim.entropy(region)
+    delta = 200 * l * EPS
+    for t in range(B):
+        err = float(np.max(np.abs(np.sort(got[t]) - np.sort(lams[t]))))
+        assert err <= delta, (t, err)
+        assert abs(S[t] - h(lams[t]).sum()) <= entropy_bound(lams[t], delta)
+    sim.close()
+
+
+def test_known_spectrum_with_tiny_couplings_blocked():
+    """The tiny-coupling states of the test above at n = 650 in a batch of 40 (the blocked
+    reduction): reflectors of columns with entries ~1e-160 keep the spectrum exact."""
+    half, B = 325, 40
+    L, N = 4 * half + 64, 2 * half + 32
+    rng = np.random.default_rng(half)
+    A1 = list(range(0, half))
+    A2 = list(range(L // 2, L // 2 + half))
+    region = sorted(A1 + A2)
+    sim = make_sim(1, L, n_traj=B, N=N, occupied=list(range(N)))
+    lams, Us = [], []
+    for t in range(B):
+        eps = (1e-160, 1e-100, 1e-30, 0.3)[t % 4]
+        lam = spectrum_mix(2 * half, rng)
+        lams.append(lam)
+        Us.append(coupled_state(L, N, A1, A2, lam, eps, rng))
+    sim.set_state(np.concatenate(Us), 0)
+    got = sim.region_spectrum(region)
+    for t in range(B):
+        err = float(np.max(np.abs(np.sort(got[t]) - np.sort(lams[t]))))
+        assert err <= 200 * len(region) * EPS, (t, err)
+    sim.close()
