@@ -221,8 +221,8 @@ __global__ __launch_bounds__(256) void tri_sweep_kernel(EigWork W, int n, int k)
 // the reflector slots v (the hemv output y stays in p).
 constexpr int TRD_REFLECT_THREADS = 1024;
 constexpr int TRD_ZCH = 16;        // row chunks of the z partial sums
-constexpr int TRD_PANEL_ROWS = 256;
-static_assert(TRD_ZCH == 16 && TRD_PANEL_ROWS == 256, "trd_panel_elems sizes the panel storage for these");
+constexpr int TRD_PANEL_ROWS = 64;  // rows per workgroup of the row pass
+static_assert(TRD_ZCH == 16 && TRD_PANEL_ROWS == 64, "trd_panel_elems sizes the panel storage for these");
 
 __device__ __forceinline__ cplx cmul_conj_a(cplx a, cplx x) {  // conj(a) x
   return cplx{a.re * x.re + a.im * x.im, a.re * x.im - a.im * x.re};
@@ -232,7 +232,7 @@ __device__ __forceinline__ cplx cmul(cplx a, cplx x) {
 }
 
 struct PanelPtrs {
-  cplx *X, *Y, *zpart, *kpart;
+  cplx *X, *Y, *zpart, *kpart, *part, *dotpart;
 };
 __device__ __forceinline__ PanelPtrs panel_ptrs(const EigWork &W, int b, int n) {
   PanelPtrs q;
@@ -240,12 +240,111 @@ __device__ __forceinline__ PanelPtrs panel_ptrs(const EigWork &W, int b, int n) 
   q.Y = q.X + (long)2 * TRD_NB * n;
   q.zpart = q.Y + (long)2 * TRD_NB * n;
   q.kpart = q.zpart + TRD_ZCH * 2 * TRD_NB;
+  q.part = q.kpart + (n + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS;
+  q.dotpart = q.part + (long)((n + 63) / 64) * n;
   return q;
 }
 
-// y_raw = A v_r over columns c > k0 + r; z partial sums over row chunks (workgroups < TRD_ZCH).
+// y = A v_r over columns c > k0 + r from the lower triangle only: with T the trailing block,
+//   y_c = sum_{i >= c} conj(T_ic) v_i + sum_{i < c} T_ci v_i,
+// the first sum read down column c, the second from the entries T_ci (c > i) of earlier
+// columns.  The lower triangle is cut into 64 x 64 tiles (row tile t >= column tile p), one
+// workgroup each: the tile is staged in LDS, and the workgroup writes its row sums
+// sum_c T_ic v_c (strictly below the diagonal) to part[p][i] and its column sums
+// sum_i conj(T_ic) v_i (on and below the diagonal) to dotpart[t][c]; the row pass adds them up
+// in a fixed order.  Workgroups below TRD_ZCH also form the partial sums of z = (W^+ v, V^+ v)
+// over row chunks.
+constexpr int TRD_TILE = 64;
+
+__device__ __forceinline__ void lower_tile(long id, int &t, int &p) {  // id = t (t + 1) / 2 + p
+  int c = (int)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+  while ((long)c * (c + 1) / 2 > id) --c;
+  while ((long)(c + 1) * (c + 2) / 2 <= id) ++c;
+  t = c;
+  p = (int)(id - (long)c * (c + 1) / 2);
+}
+
+constexpr int TRD_HEMV_THREADS = 512;
+
+__global__ __launch_bounds__(TRD_HEMV_THREADS) void trd_hemv_kernel(EigWork W, int n, int k0, int jp, int r) {
+  constexpr int NW = TRD_HEMV_THREADS / 64, SUB = TRD_HEMV_THREADS / TRD_TILE;
+  const int b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = k0 + r;
+  if (W.tau[2 * b + (k & 1)] == 0.0) return;
+  const PanelPtrs q = panel_ptrs(W, b, n);
+  const cplx *v = q.X + (long)r * n;
+  if (blockIdx.x < TRD_ZCH && r > 0) {  // z_t = w_t^+ v, z_{r+t} = v_t^+ v over this row chunk
+    const int rows = n - k - 1, csz = (rows + TRD_ZCH - 1) / TRD_ZCH;
+    const int i0 = k + 1 + blockIdx.x * csz, i1 = min(n, i0 + csz);
+    for (int t2 = wave; t2 < 2 * r; t2 += NW) {
+      const cplx *c = q.X + (long)(t2 < r ? jp + t2 : t2 - r) * n;
+      double zr = 0.0, zi = 0.0;
+      for (int i = i0 + lane; i < i1; i += 64) {
+        const cplx x = cmul_conj_a(c[i], v[i]);
+        zr += x.re;
+        zi += x.im;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        zr += __shfl_down(zr, o, 64);
+        zi += __shfl_down(zi, o, 64);
+      }
+      if (lane == 0) q.zpart[blockIdx.x * 2 * TRD_NB + t2] = cplx{zr, zi};
+    }
+  }
+  const int c0 = k + 1, T = (n - c0 + TRD_TILE - 1) / TRD_TILE;
+  if ((long)blockIdx.x >= (long)T * (T + 1) / 2) return;  // uniform over the workgroup
+  int t, p;
+  lower_tile(blockIdx.x, t, p);
+  const int r0 = c0 + TRD_TILE * t, cb = c0 + TRD_TILE * p;
+  const cplx *A = W.A + (long)b * n * n;
+  // tile[c][i]: row r0 + i, column cb + c; a row stride of 72 entries (8 mod 16) spreads both
+  // read patterns below over all LDS banks
+  __shared__ cplx tile[TRD_TILE][TRD_TILE + 8];
+  __shared__ cplx vrow[TRD_TILE], vcol[TRD_TILE];
+  for (int c = wave; c < TRD_TILE; c += NW) {
+    const int row = r0 + lane, col = cb + c;
+    tile[c][lane] = (row < n && col < n) ? A[row + (long)col * n] : cplx{0.0, 0.0};
+  }
+  if (tid < TRD_TILE) vrow[tid] = r0 + tid < n ? v[r0 + tid] : cplx{0.0, 0.0};
+  else if (tid < 2 * TRD_TILE) vcol[tid - TRD_TILE] = cb + tid - TRD_TILE < n ? v[cb + tid - TRD_TILE] : cplx{0.0, 0.0};
+  __syncthreads();
+  const bool diag = t == p;
+  // row / column o of the tile; the other index runs over u = qq, qq + SUB, ... (the SUB threads
+  // of one o read neighbouring LDS entries)
+  const int o = tid / SUB, qq = tid % SUB;
+  double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+  for (int u = qq; u < TRD_TILE; u += SUB) {
+    if (!diag || o > u) {  // row sums: T_{o,u} v_u, strictly lower
+      const cplx a = tile[u][o], x = vcol[u];
+      ar += a.re * x.re - a.im * x.im;
+      ai += a.re * x.im + a.im * x.re;
+    }
+    if (!diag || u >= o) {  // column sums: conj(T_{u,o}) v_u, on and below the diagonal
+      const cplx a = tile[o][u], x = vrow[u];
+      dr += a.re * x.re + a.im * x.im;
+      di += a.re * x.im - a.im * x.re;
+    }
+  }
+  for (int m = 1; m < SUB; m <<= 1) {
+    ar += __shfl_xor(ar, m, 64);
+    ai += __shfl_xor(ai, m, 64);
+    dr += __shfl_xor(dr, m, 64);
+    di += __shfl_xor(di, m, 64);
+  }
+  if (qq == 0) {
+    if (r0 + o < n) q.part[(long)p * n + r0 + o] = cplx{ar, ai};
+    if (cb + o < n) q.dotpart[(long)t * n + cb + o] = cplx{dr, di};
+  }
+}
+
+// The same A v from whole columns (trailing blocks below TRD_TILED_MIN): one wave per CPW
+// columns reads rows k0 + r + 1 .. n-1 of each and writes y_c = sum_i conj(A_ic) v_i (A Hermitian)
+// to W.p; twice the bytes of the tiled form, but far fewer, fuller workgroups for small blocks.
+constexpr int TRD_TILED_MIN = 1024;
+
 template <int CPW>
-__global__ __launch_bounds__(256) void trd_hemv_kernel(EigWork W, int n, int k0, int jp, int r) {
+__global__ __launch_bounds__(256) void trd_hemv_cols_kernel(EigWork W, int n, int k0, int jp, int r) {
   const int b = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = k0 + r;
   if (W.tau[2 * b + (k & 1)] == 0.0) return;
@@ -300,23 +399,29 @@ __global__ __launch_bounds__(256) void trd_hemv_kernel(EigWork W, int n, int k0,
   }
 }
 
-// Rows i >= k = k0 + r + 1 of matrix blockIdx.y (TRD_PANEL_ROWS per workgroup), for reflector r:
-//   y_i = y_raw_i - sum_{t<r} (v_t[i] z_t + w_t[i] z_{r+t})      (into W.v)
+// Rows i >= k = k0 + r + 1 of matrix blockIdx.y (TRD_PANEL_ROWS per workgroup, 4 threads per
+// row sharing its sums), for reflector r:
+//   y_i = (A v_r)_i - sum_{t<r} (v_t[i] z_t + w_t[i] z_{r+t})     (into W.v)
 //   partial sum of conj(v_r[i]) y_i                             (into kpart)
 //   with_col: a_i = A_ik - sum_{t<r} (v_t[i] conj(w_t[k]) + w_t[i] conj(v_t[k]))
 //                        - tau_r (v_r[i] conj(y_k) + y_i conj(v_r[k]))   (into column k)
-__global__ __launch_bounds__(TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, int n, int k0, int jp, int r,
-                                                                   int with_col) {
-  const int b = blockIdx.y, tid = threadIdx.x;
+// tiled: (A v_r)_i is the sum of the tiles' column sums dotpart[t][i] (t >= the tile of i) and row
+// sums part[p][i] (p <= it), in a fixed order; otherwise it is W.p[i].
+__global__ __launch_bounds__(4 * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, int n, int k0, int jp, int r,
+                                                                       int with_col, int tiled) {
+  constexpr int NT = 4 * TRD_PANEL_ROWS;
+  const int b = blockIdx.y, tid = threadIdx.x, sub = tid & 3;
   const int k = k0 + r + 1;
-  const int i = k + blockIdx.x * TRD_PANEL_ROWS + tid;
+  const int i = k + blockIdx.x * TRD_PANEL_ROWS + (tid >> 2);
+  const bool live = i < n;
+  const int row = live ? i : n - 1;  // rows past the end compute on the last row, unwritten
   const PanelPtrs q = panel_ptrs(W, b, n);
   const double tp = W.tau[2 * b + ((k - 1) & 1)];
   __shared__ cplx zs[2 * TRD_NB], rowk[2 * TRD_NB];
-  __shared__ double red[TRD_PANEL_ROWS / 64];
+  __shared__ double red[NT / 64];
   __shared__ cplx sh_yk;
   if (tp != 0.0)
-    for (int t2 = tid; t2 < 2 * r; t2 += TRD_PANEL_ROWS) {  // z summed over the row chunks in order
+    for (int t2 = tid; t2 < 2 * r; t2 += NT) {  // z summed over the row chunks in order
       cplx acc{0.0, 0.0};
       for (int c = 0; c < TRD_ZCH; ++c) {
         const cplx x = q.zpart[c * 2 * TRD_NB + t2];
@@ -326,52 +431,86 @@ __global__ __launch_bounds__(TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, in
       zs[t2] = acc;
     }
   if (with_col)
-    for (int t2 = tid; t2 < 2 * r; t2 += TRD_PANEL_ROWS)  // v_t[k], w_t[k]
+    for (int t2 = tid; t2 < 2 * r; t2 += NT)  // v_t[k], w_t[k]
       rowk[t2] = q.X[k + (long)(t2 < r ? t2 : jp + t2 - r) * n];
   __syncthreads();
-  const cplx *yraw = W.p + (long)b * n;
   cplx *ycor = W.v + (long)b * 2 * n;
-  auto y_at = [&](int row) {
-    cplx yv = yraw[row];
-    for (int t = 0; t < r; ++t) {
-      const cplx a = cmul(q.X[row + (long)t * n], zs[t]), c = cmul(q.X[row + (long)(jp + t) * n], zs[r + t]);
-      yv.re -= a.re + c.re;
-      yv.im -= a.im + c.im;
+  const int T = (n - k + TRD_TILE - 1) / TRD_TILE;
+  // y at row rw, summed by the 4 threads of a quad (each takes every 4th term)
+  const cplx *ycols = W.p + (long)b * n;
+  auto y_at = [&](int rw) {
+    double yr = 0.0, yi = 0.0;
+    if (tiled) {
+      const int pr = (rw - k) / TRD_TILE;
+      for (int t = pr + sub; t < T; t += 4) {
+        const cplx x = q.dotpart[(long)t * n + rw];
+        yr += x.re;
+        yi += x.im;
+      }
+      for (int p = sub; p <= pr; p += 4) {
+        const cplx x = q.part[(long)p * n + rw];
+        yr += x.re;
+        yi += x.im;
+      }
+    } else if (sub == 0) {
+      yr = ycols[rw].re;
+      yi = ycols[rw].im;
     }
-    return yv;
+    for (int t = sub; t < r; t += 4) {
+      const cplx a = cmul(q.X[rw + (long)t * n], zs[t]), c = cmul(q.X[rw + (long)(jp + t) * n], zs[r + t]);
+      yr -= a.re + c.re;
+      yi -= a.im + c.im;
+    }
+    for (int m = 1; m < 4; m <<= 1) {
+      yr += __shfl_xor(yr, m, 64);
+      yi += __shfl_xor(yi, m, 64);
+    }
+    return cplx{yr, yi};
   };
-  if (tid == 0) sh_yk = tp != 0.0 ? y_at(k) : cplx{0.0, 0.0};
+  if (tid < 4) {
+    const cplx yk = tp != 0.0 ? y_at(k) : cplx{0.0, 0.0};
+    if (tid == 0) sh_yk = yk;
+  }
   __syncthreads();
   const cplx *vr = q.X + (long)r * n;
   double kr = 0.0, ki = 0.0;
-  if (i < n) {
-    cplx yi{0.0, 0.0};
-    if (tp != 0.0) {
-      yi = y_at(i);
-      ycor[i] = yi;
-      const cplx x = cmul_conj_a(vr[i], yi);
+  cplx yv{0.0, 0.0};
+  if (tp != 0.0) {
+    yv = y_at(row);
+    if (live && sub == 0) {
+      ycor[row] = yv;
+      const cplx x = cmul_conj_a(vr[row], yv);
       kr = x.re;
       ki = x.im;
     }
-    if (with_col) {
-      cplx *col = W.A + (long)b * n * n + (long)k * n;
-      cplx a = col[i];
-      for (int t = 0; t < r; ++t) {
-        const cplx vi = q.X[i + (long)t * n], wi = q.X[i + (long)(jp + t) * n];
-        const cplx vk = rowk[t], wk = rowk[r + t];
-        a.re -= (vi.re * wk.re + vi.im * wk.im) + (wi.re * vk.re + wi.im * vk.im);
-        a.im -= (vi.im * wk.re - vi.re * wk.im) + (wi.im * vk.re - wi.re * vk.im);
-      }
+  }
+  if (with_col) {
+    cplx *col = W.A + (long)b * n * n + (long)k * n;
+    double sr = 0.0, si = 0.0;
+    for (int t = sub; t < r; t += 4) {
+      const cplx vi = q.X[row + (long)t * n], wi = q.X[row + (long)(jp + t) * n];
+      const cplx vk = rowk[t], wk = rowk[r + t];
+      sr += (vi.re * wk.re + vi.im * wk.im) + (wi.re * vk.re + wi.im * vk.im);
+      si += (vi.im * wk.re - vi.re * wk.im) + (wi.im * vk.re - wi.re * vk.im);
+    }
+    for (int m = 1; m < 4; m <<= 1) {
+      sr += __shfl_xor(sr, m, 64);
+      si += __shfl_xor(si, m, 64);
+    }
+    if (live && sub == 0) {
+      cplx a = col[row];
+      a.re -= sr;
+      a.im -= si;
       if (tp != 0.0) {  // - tau (v_r[i] conj(y_k) + y_i conj(v_r[k]))
-        const cplx vi = vr[i], vk = vr[k], yk = sh_yk;
-        a.re -= tp * ((vi.re * yk.re + vi.im * yk.im) + (yi.re * vk.re + yi.im * vk.im));
-        a.im -= tp * ((vi.im * yk.re - vi.re * yk.im) + (yi.im * vk.re - yi.re * vk.im));
+        const cplx vi = vr[row], vk = vr[k], yk = sh_yk;
+        a.re -= tp * ((vi.re * yk.re + vi.im * yk.im) + (yv.re * vk.re + yv.im * vk.im));
+        a.im -= tp * ((vi.im * yk.re - vi.re * yk.im) + (yv.im * vk.re - yv.re * vk.im));
       }
-      col[i] = a;
+      col[row] = a;
     }
   }
-  kr = block_sum_nt<TRD_PANEL_ROWS>(kr, red);
-  ki = block_sum_nt<TRD_PANEL_ROWS>(ki, red);
+  kr = block_sum_nt<NT>(kr, red);
+  ki = block_sum_nt<NT>(ki, red);
   if (tid == 0) q.kpart[blockIdx.x] = cplx{kr, ki};
 }
 
@@ -572,23 +711,30 @@ hipError_t tridiagonalize_blocked(const EigWork &w, int n, int B, hipStream_t s)
     for (int j = 0; j <= jp; ++j) {
       if (j >= 1) {  // y of reflector j - 1 and column k0 + j corrected by the panel
         const int rows = n - (k0 + j);
+        const int tiled = rows >= TRD_TILED_MIN ? 1 : 0;  // the form of A v for reflector j - 1 (m = rows)
         hipLaunchKernelGGL(trd_panel_kernel, dim3((unsigned)((rows + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS), B),
-                           dim3(TRD_PANEL_ROWS), 0, s, w, n, k0, jp, j - 1, j < jp ? 1 : 0);
+                           dim3(4 * TRD_PANEL_ROWS), 0, s, w, n, k0, jp, j - 1, j < jp ? 1 : 0, tiled);
       }
       hipLaunchKernelGGL(trd_reflect_kernel<TRD_REFLECT_THREADS>, one, rt, 0, s, w, n, k0, jp, j);
       if ((err = hipGetLastError()) != hipSuccess) return err;
       if (j == jp) break;
       const long m = n - (k0 + j) - 1;
-      long gx;
-      if ((gx = (m + 15) / 16) * B >= 512)
-        hipLaunchKernelGGL(trd_hemv_kernel<4>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0, s,
-                           w, n, k0, jp, j);
-      else if ((gx = (m + 7) / 8) * B >= 512)
-        hipLaunchKernelGGL(trd_hemv_kernel<2>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0, s,
-                           w, n, k0, jp, j);
-      else
-        hipLaunchKernelGGL(trd_hemv_kernel<1>, dim3((unsigned)std::max<long>((m + 3) / 4, TRD_ZCH), B),
-                           dim3(256), 0, s, w, n, k0, jp, j);
+      if (m >= TRD_TILED_MIN) {
+        const long T = (m + TRD_TILE - 1) / TRD_TILE;
+        hipLaunchKernelGGL(trd_hemv_kernel, dim3((unsigned)std::max<long>(T * (T + 1) / 2, TRD_ZCH), B),
+                           dim3(TRD_HEMV_THREADS), 0, s, w, n, k0, jp, j);
+      } else {
+        long gx;
+        if ((gx = (m + 15) / 16) * B >= 512)
+          hipLaunchKernelGGL(trd_hemv_cols_kernel<4>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0,
+                             s, w, n, k0, jp, j);
+        else if ((gx = (m + 7) / 8) * B >= 512)
+          hipLaunchKernelGGL(trd_hemv_cols_kernel<2>, dim3((unsigned)std::max<long>(gx, TRD_ZCH), B), dim3(256), 0,
+                             s, w, n, k0, jp, j);
+        else
+          hipLaunchKernelGGL(trd_hemv_cols_kernel<1>, dim3((unsigned)std::max<long>((m + 3) / 4, TRD_ZCH), B),
+                             dim3(256), 0, s, w, n, k0, jp, j);
+      }
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     // A22 -= [V W] [W V]^+ over the trailing block
