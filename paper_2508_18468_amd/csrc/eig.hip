@@ -20,8 +20,8 @@
 //                Hermitian A.
 // Every sweep reads and writes the trailing matrix once (HBM-bound).  Batches
 // with enough work take the blocked form below instead (panels of TRD_NB
-// reflectors, the trailing matrix only read per reflector and written once per
-// panel by a GEMM), which halves that traffic.
+// reflectors, only the lower triangle of the trailing matrix read per reflector,
+// the matrix written once per panel by a GEMM): about a quarter of that traffic.
 // Bisection: one lane per eigenvalue when the batch offers enough of them,
 // otherwise one wave per eigenvalue that splits its interval at 64 points per
 // Sturm pass (65-fold narrowing per pass instead of 2-fold).
@@ -207,9 +207,10 @@ __global__ __launch_bounds__(256) void tri_sweep_kernel(EigWork W, int n, int k)
 // reduced.  At the end of the panel the trailing matrix takes all of the panel's reflectors in
 // one GEMM, A -= [V W] [W V]^+, on the matrix cores; the last LDS_MAX_N columns are reduced in
 // LDS.  For reflector r of a panel (column k0 + r) three launches:
-//   trd_hemv(r)    grid: y_c = sum_i conj(A_ic) v_i over columns c > k0 + r (one wave per
-//                  group of columns), and, in the first TRD_ZCH workgroups, partial sums over
-//                  row chunks of z = (W^+ v, V^+ v) against the panel's earlier reflectors;
+//   trd_hemv(r)    grid: A v over the trailing block of columns c > k0 + r (from 64 x 64 tiles
+//                  of its lower triangle, or from whole columns when the block is small), and,
+//                  in the first TRD_ZCH workgroups, partial sums over row chunks of
+//                  z = (W^+ v, V^+ v) against the panel's earlier reflectors;
 //   trd_panel(r+1) grid over rows i >= k = k0 + r + 1: y_i corrected by the panel,
 //                  partial sums of v^+ y, and column k corrected by the panel except for the
 //                  part of reflector r's w that needs v^+ y;
