@@ -27,7 +27,9 @@ constexpr int NB = CHOL_NB;
 // conj(G_ki) G_kj / G_kk from the trailing upper triangle, one barrier per
 // step, each thread owning a fixed 4 x 4 set of (row, column) positions; the
 // rows of R are scaled by 1/sqrt(G_kk) afterwards.  The inverse is formed by
-// back substitution with four lanes per column.
+// back substitution with four lanes per column and kept transposed in the free
+// lower triangle of the same LDS array (its diagonal apart), so that two
+// workgroups fit on a compute unit.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, int N, int c0, int w,
                                                          int *flag, const double *skip_if_le,
                                                          double skip_thr) {
@@ -35,8 +37,10 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
   const int b = blockIdx.x, tid = threadIdx.x;
   cplx *Gb = G + (long)b * N * N;
   cplx *Rb = Rinv + (long)b * N * N;
-  __shared__ cplx a[NB][NB + 1];  // a[c][r] = element (row r, col c) of the block
-  __shared__ cplx x[NB][NB + 1];  // x[c][r] = element (r, c) of the inverse
+  // a[c][r], r <= c: element (row r, col c) of the block, then of R; a[r][c], r < c: element
+  // (r, c) of R^{-1}; xd: the diagonal of R^{-1}
+  __shared__ cplx a[NB][NB + 1];
+  __shared__ double xd[NB];
   __shared__ double rs[NB];       // sqrt of the pivots
   __shared__ int bad;
   if (tid == 0) bad = 0;
@@ -82,15 +86,16 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
       a[c][r] = r == c ? cplx{rs[r], 0.0} : cplx{a[c][r].re * sc, a[c][r].im * sc};
     }
   __syncthreads();
-  // inverse of the upper triangular block: column j by lanes 4j .. 4j+3
+  // inverse of the upper triangular block: column j by lanes 4j .. 4j+3; element (l, j) of the
+  // inverse (l < j) lives at a[l][j]
   const int j = tid >> 2, q = tid & 3;
   if (j < w) {
-    for (int i = j + 1 + q; i < w; i += 4) x[j][i] = cplx{0.0, 0.0};
-    x[j][j] = cplx{1.0 / a[j][j].re, 0.0};
+    const double dj = 1.0 / a[j][j].re;
+    if (q == 0) xd[j] = dj;
     for (int i = j - 1; i >= 0; --i) {
       double sr = 0.0, si = 0.0;
       for (int l = i + 1 + q; l <= j; l += 4) {
-        const cplx r = a[l][i], t = x[j][l];
+        const cplx r = a[l][i], t = l == j ? cplx{dj, 0.0} : a[l][j];
         sr += r.re * t.re - r.im * t.im;
         si += r.re * t.im + r.im * t.re;
       }
@@ -99,14 +104,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, in
       sr += __shfl_xor(sr, 2, 64);
       si += __shfl_xor(si, 2, 64);
       const double inv = 1.0 / a[i][i].re;
-      x[j][i] = cplx{-sr * inv, -si * inv};  // the four lanes store the same value
+      a[i][j] = cplx{-sr * inv, -si * inv};  // the four lanes store the same value
     }
   }
   __syncthreads();
   for (int c = tid >> 6; c < w; c += 4)
     for (int r = tid & 63; r < w; r += 64) {
       if (r <= c) Gb[(c0 + r) + (long)(c0 + c) * N] = a[c][r];
-      Rb[(c0 + r) + (long)(c0 + c) * N] = x[c][r];
+      Rb[(c0 + r) + (long)(c0 + c) * N] = r < c ? a[r][c] : (r == c ? cplx{xd[r], 0.0} : cplx{0.0, 0.0});
     }
   if (tid == 0 && bad) atomicOr(flag, 1);
 }
