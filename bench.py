@@ -197,17 +197,27 @@ def run_large(args):
         obs[f"S_l{len(r)}"] = [float(x) for x in S]
     sim.close()
     prop_ms, prop_n = phases["propagate"]
-    if rk4 and w.protocol == 1:  # nearest-neighbour passes: not a matrix-core kernel
-        flops = None
-    elif factored:  # algorithmic flops of the factored application
-        if w.dim == 2:
+    per_launch_s = prop_ms / prop_n * 1e-3 if prop_n else None
+    if (rk4 and w.protocol == 1) or (factored and w.dim == 1):
+        # memory-bound passes: RK4 = Born read (16 L N B bytes) + the first stage (reads U, writes
+        # V: 32 L N B) + three stages that read U and V and write V' (48 L N B each); ring band =
+        # one read and one write of U
+        alg = (192.0 if rk4 and w.protocol == 1 else 32.0) * w.L * w.N * B
+        achieved = alg / per_launch_s / 1e9 if per_launch_s else None
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": None,
+                "kernel": "rk4 step" if rk4 and w.protocol == 1 else "ring band stencil",
+                "algorithmic_bytes_per_launch": alg}
+    else:
+        if factored:  # the two Kronecker factors as GEMMs of depth Lx and Ly
             flops = 8.0 * (w.Lx + w.Ly) * w.L * w.N * B
         else:
-            flops = 8.0 * (2 * band + 1) * w.L * w.N * B
-    else:
-        flops = 8.0 * w.L * w.L * w.N * B
-    tf = flops / (prop_ms / prop_n * 1e-3) / 1e12 if (prop_n and flops) else None
-    peak = PEAK_FP64_TFLOPS if (precision == mfq.FP64 or factored) else PEAK_FP32_TFLOPS
+            flops = 8.0 * w.L * w.L * w.N * B
+        tf = flops / per_launch_s / 1e12 if per_launch_s else None
+        peak = PEAK_FP64_TFLOPS if (precision == mfq.FP64 or factored) else PEAK_FP32_TFLOPS
+        roof = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                "frac": tf / peak if tf else None, "traffic": None,
+                "kernel": "propagator", "algorithmic_flops_per_launch": flops}
     value = B * w.L * w.N * steps / T
     # the paper's one measured rate: a homodyne trajectory at L = 16384 over t in [0, L] in about
     # 130 h on one A100, i.e. 9.4e7 L*N*steps/s (other hardware: context, not the target)
@@ -221,9 +231,7 @@ def run_large(args):
                       "gammas": list(w.gammas), "protocol": "projective" if w.protocol == 0 else "homodyne",
                       "dt": w.dt, "precision": prec_name, "integrator": args.integrator,
                       "hours_per_trajectory_to_t_eq_L": (T / steps / B) * (w.L / w.dt) / 3600.0},
-           "roofline": {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s",
-                        "frac": tf / peak if tf else None, "traffic": None,
-                        "kernel": "propagator", "algorithmic_flops_per_launch": flops},
+           "roofline": roof,
            "phase_ms_per_step": {k: v[0] / steps for k, v in phases.items()},
            "observations": obs}
     print(json.dumps(out))

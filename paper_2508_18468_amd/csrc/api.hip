@@ -420,8 +420,9 @@ bool factored_propagator(const mfq_ctx *c) {
 
 // Enqueue one step on the stream; the step index is read on the device as
 // *step_dev + step_offset.  The propagated state lands in X[1-cur] (dense form,
-// ring band) or, for the torus factors, back in X[cur]; measurement and the
-// re-orthonormalisation end in the same buffer, which becomes the current one.
+// ring band) or, for the torus factors and RK4, back in X[cur]; the measurement
+// works in place, and Cholesky-QR2 leaves the orthonormal factor in the other
+// buffer, which becomes the current one.
 mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int step_offset) {
   const int L = c->L, N = c->N, B = c->B;
   cplx *Xa = c->X[c->cur], *Xb = c->X[1 - c->cur];
