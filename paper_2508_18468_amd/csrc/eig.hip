@@ -249,8 +249,9 @@ __device__ __forceinline__ PanelPtrs panel_ptrs(const EigWork &W, int b, int n) 
 // y = A v_r over columns c > k0 + r from the lower triangle only: with T the trailing block,
 //   y_c = sum_{i >= c} conj(T_ic) v_i + sum_{i < c} T_ci v_i,
 // the first sum read down column c, the second from the entries T_ci (c > i) of earlier
-// columns.  The lower triangle is cut into 64 x 64 tiles (row tile t >= column tile p), one
-// workgroup each: the tile is staged in LDS, and the workgroup writes its row sums
+// columns.  The lower triangle is cut into 64 x 64 tiles (row tile t >= column tile p), TRD_TPW
+// consecutive ones per workgroup: each tile is staged in LDS (the next one loaded into registers
+// meanwhile), and the workgroup writes its row sums
 // sum_c T_ic v_c (strictly below the diagonal) to part[p][i] and its column sums
 // sum_i conj(T_ic) v_i (on and below the diagonal) to dotpart[t][c]; the row pass adds them up
 // in a fixed order.  Workgroups below TRD_ZCH also form the partial sums of z = (W^+ v, V^+ v)
@@ -266,6 +267,7 @@ __device__ __forceinline__ void lower_tile(long id, int &t, int &p) {  // id = t
 }
 
 constexpr int TRD_HEMV_THREADS = 512;
+constexpr int TRD_TPW = 4;  // tiles per workgroup, one loaded while the previous is reduced
 
 __global__ __launch_bounds__(TRD_HEMV_THREADS) void trd_hemv_kernel(EigWork W, int n, int k0, int jp, int r) {
   constexpr int NW = TRD_HEMV_THREADS / 64, SUB = TRD_HEMV_THREADS / TRD_TILE;
@@ -293,49 +295,72 @@ __global__ __launch_bounds__(TRD_HEMV_THREADS) void trd_hemv_kernel(EigWork W, i
     }
   }
   const int c0 = k + 1, T = (n - c0 + TRD_TILE - 1) / TRD_TILE;
-  if ((long)blockIdx.x >= (long)T * (T + 1) / 2) return;  // uniform over the workgroup
-  int t, p;
-  lower_tile(blockIdx.x, t, p);
-  const int r0 = c0 + TRD_TILE * t, cb = c0 + TRD_TILE * p;
+  const long ntile = (long)T * (T + 1) / 2;
+  const long id0 = (long)blockIdx.x * TRD_TPW;
+  if (id0 >= ntile) return;  // uniform over the workgroup
   const cplx *A = W.A + (long)b * n * n;
   // tile[c][i]: row r0 + i, column cb + c; a row stride of 72 entries (8 mod 16) spreads both
   // read patterns below over all LDS banks
   __shared__ cplx tile[TRD_TILE][TRD_TILE + 8];
   __shared__ cplx vrow[TRD_TILE], vcol[TRD_TILE];
-  for (int c = wave; c < TRD_TILE; c += NW) {
-    const int row = r0 + lane, col = cb + c;
-    tile[c][lane] = (row < n && col < n) ? A[row + (long)col * n] : cplx{0.0, 0.0};
-  }
-  if (tid < TRD_TILE) vrow[tid] = r0 + tid < n ? v[r0 + tid] : cplx{0.0, 0.0};
-  else if (tid < 2 * TRD_TILE) vcol[tid - TRD_TILE] = cb + tid - TRD_TILE < n ? v[cb + tid - TRD_TILE] : cplx{0.0, 0.0};
-  __syncthreads();
-  const bool diag = t == p;
+  // the next tile is loaded into registers while the current one is reduced from LDS
+  constexpr int PER = TRD_TILE / NW;  // columns per wave
+  cplx nxt[PER], vnx{0.0, 0.0};
+  auto fetch = [&](long id) {
+    int tt, pp;
+    lower_tile(id, tt, pp);
+    const int rr0 = c0 + TRD_TILE * tt, cc0 = c0 + TRD_TILE * pp;
+    const int row = rr0 + lane;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int col = cc0 + wave + NW * m;
+      nxt[m] = (row < n && col < n) ? A[row + (long)col * n] : cplx{0.0, 0.0};
+    }
+    if (tid < TRD_TILE) vnx = rr0 + tid < n ? v[rr0 + tid] : cplx{0.0, 0.0};
+    else if (tid < 2 * TRD_TILE) vnx = cc0 + tid - TRD_TILE < n ? v[cc0 + tid - TRD_TILE] : cplx{0.0, 0.0};
+  };
+  fetch(id0);
   // row / column o of the tile; the other index runs over u = qq, qq + SUB, ... (the SUB threads
   // of one o read neighbouring LDS entries)
   const int o = tid / SUB, qq = tid % SUB;
-  double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
+  for (int s = 0; s < TRD_TPW; ++s) {
+    const long id = id0 + s;
+    if (id >= ntile) break;  // uniform
+    __syncthreads();         // the previous tile's reads are done
 #pragma unroll
-  for (int u = qq; u < TRD_TILE; u += SUB) {
-    if (!diag || o > u) {  // row sums: T_{o,u} v_u, strictly lower
-      const cplx a = tile[u][o], x = vcol[u];
-      ar += a.re * x.re - a.im * x.im;
-      ai += a.re * x.im + a.im * x.re;
+    for (int m = 0; m < PER; ++m) tile[wave + NW * m][lane] = nxt[m];
+    if (tid < TRD_TILE) vrow[tid] = vnx;
+    else if (tid < 2 * TRD_TILE) vcol[tid - TRD_TILE] = vnx;
+    __syncthreads();
+    if (s + 1 < TRD_TPW && id + 1 < ntile) fetch(id + 1);
+    int t, p;
+    lower_tile(id, t, p);
+    const int r0 = c0 + TRD_TILE * t, cb = c0 + TRD_TILE * p;
+    const bool diag = t == p;
+    double ar = 0.0, ai = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int u = qq; u < TRD_TILE; u += SUB) {
+      if (!diag || o > u) {  // row sums: T_{o,u} v_u, strictly lower
+        const cplx a = tile[u][o], x = vcol[u];
+        ar += a.re * x.re - a.im * x.im;
+        ai += a.re * x.im + a.im * x.re;
+      }
+      if (!diag || u >= o) {  // column sums: conj(T_{u,o}) v_u, on and below the diagonal
+        const cplx a = tile[o][u], x = vrow[u];
+        dr += a.re * x.re + a.im * x.im;
+        di += a.re * x.im - a.im * x.re;
+      }
     }
-    if (!diag || u >= o) {  // column sums: conj(T_{u,o}) v_u, on and below the diagonal
-      const cplx a = tile[o][u], x = vrow[u];
-      dr += a.re * x.re + a.im * x.im;
-      di += a.re * x.im - a.im * x.re;
+    for (int m = 1; m < SUB; m <<= 1) {
+      ar += __shfl_xor(ar, m, 64);
+      ai += __shfl_xor(ai, m, 64);
+      dr += __shfl_xor(dr, m, 64);
+      di += __shfl_xor(di, m, 64);
     }
-  }
-  for (int m = 1; m < SUB; m <<= 1) {
-    ar += __shfl_xor(ar, m, 64);
-    ai += __shfl_xor(ai, m, 64);
-    dr += __shfl_xor(dr, m, 64);
-    di += __shfl_xor(di, m, 64);
-  }
-  if (qq == 0) {
-    if (r0 + o < n) q.part[(long)p * n + r0 + o] = cplx{ar, ai};
-    if (cb + o < n) q.dotpart[(long)t * n + cb + o] = cplx{dr, di};
+    if (qq == 0) {
+      if (r0 + o < n) q.part[(long)p * n + r0 + o] = cplx{ar, ai};
+      if (cb + o < n) q.dotpart[(long)t * n + cb + o] = cplx{dr, di};
+    }
   }
 }
 
@@ -721,8 +746,8 @@ hipError_t tridiagonalize_blocked(const EigWork &w, int n, int B, hipStream_t s)
       if (j == jp) break;
       const long m = n - (k0 + j) - 1;
       if (m >= TRD_TILED_MIN) {
-        const long T = (m + TRD_TILE - 1) / TRD_TILE;
-        hipLaunchKernelGGL(trd_hemv_kernel, dim3((unsigned)std::max<long>(T * (T + 1) / 2, TRD_ZCH), B),
+        const long T = (m + TRD_TILE - 1) / TRD_TILE, wgs = (T * (T + 1) / 2 + TRD_TPW - 1) / TRD_TPW;
+        hipLaunchKernelGGL(trd_hemv_kernel, dim3((unsigned)std::max<long>(wgs, TRD_ZCH), B),
                            dim3(TRD_HEMV_THREADS), 0, s, w, n, k0, jp, j);
       } else {
         long gx;
