@@ -222,8 +222,9 @@ __global__ __launch_bounds__(256) void tri_sweep_kernel(EigWork W, int n, int k)
 // the reflector slots v (the hemv output y stays in p).
 constexpr int TRD_REFLECT_THREADS = 1024;
 constexpr int TRD_ZCH = 16;        // row chunks of the z partial sums
-constexpr int TRD_PANEL_ROWS = 64;  // rows per workgroup of the row pass
-static_assert(TRD_ZCH == 16 && TRD_PANEL_ROWS == 64, "trd_panel_elems sizes the panel storage for these");
+constexpr int TRD_PANEL_TPR = 8;    // threads per row of the row pass
+constexpr int TRD_PANEL_ROWS = 32;  // rows per workgroup of the row pass
+static_assert(TRD_ZCH == 16 && TRD_PANEL_ROWS == 32, "trd_panel_elems sizes the panel storage for these");
 
 __device__ __forceinline__ cplx cmul_conj_a(cplx a, cplx x) {  // conj(a) x
   return cplx{a.re * x.re + a.im * x.im, a.re * x.im - a.im * x.re};
@@ -425,20 +426,20 @@ __global__ __launch_bounds__(256) void trd_hemv_cols_kernel(EigWork W, int n, in
   }
 }
 
-// Rows i >= k = k0 + r + 1 of matrix blockIdx.y (TRD_PANEL_ROWS per workgroup, 4 threads per
-// row sharing its sums), for reflector r:
+// Rows i >= k = k0 + r + 1 of matrix blockIdx.y (TRD_PANEL_ROWS per workgroup, TRD_PANEL_TPR
+// threads per row sharing its sums), for reflector r:
 //   y_i = (A v_r)_i - sum_{t<r} (v_t[i] z_t + w_t[i] z_{r+t})     (into W.v)
 //   partial sum of conj(v_r[i]) y_i                             (into kpart)
 //   with_col: a_i = A_ik - sum_{t<r} (v_t[i] conj(w_t[k]) + w_t[i] conj(v_t[k]))
 //                        - tau_r (v_r[i] conj(y_k) + y_i conj(v_r[k]))   (into column k)
 // tiled: (A v_r)_i is the sum of the tiles' column sums dotpart[t][i] (t >= the tile of i) and row
 // sums part[p][i] (p <= it), in a fixed order; otherwise it is W.p[i].
-__global__ __launch_bounds__(4 * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, int n, int k0, int jp, int r,
+__global__ __launch_bounds__(TRD_PANEL_TPR * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W, int n, int k0, int jp, int r,
                                                                        int with_col, int tiled) {
-  constexpr int NT = 4 * TRD_PANEL_ROWS;
-  const int b = blockIdx.y, tid = threadIdx.x, sub = tid & 3;
+  constexpr int NT = TRD_PANEL_TPR * TRD_PANEL_ROWS, S = TRD_PANEL_TPR;
+  const int b = blockIdx.y, tid = threadIdx.x, sub = tid % S;
   const int k = k0 + r + 1;
-  const int i = k + blockIdx.x * TRD_PANEL_ROWS + (tid >> 2);
+  const int i = k + blockIdx.x * TRD_PANEL_ROWS + tid / S;
   const bool live = i < n;
   const int row = live ? i : n - 1;  // rows past the end compute on the last row, unwritten
   const PanelPtrs q = panel_ptrs(W, b, n);
@@ -462,18 +463,18 @@ __global__ __launch_bounds__(4 * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W
   __syncthreads();
   cplx *ycor = W.v + (long)b * 2 * n;
   const int T = (n - k + TRD_TILE - 1) / TRD_TILE;
-  // y at row rw, summed by the 4 threads of a quad (each takes every 4th term)
+  // y at row rw, summed by the S threads of the row (each takes every S-th term)
   const cplx *ycols = W.p + (long)b * n;
   auto y_at = [&](int rw) {
     double yr = 0.0, yi = 0.0;
     if (tiled) {
       const int pr = (rw - k) / TRD_TILE;
-      for (int t = pr + sub; t < T; t += 4) {
+      for (int t = pr + sub; t < T; t += S) {
         const cplx x = q.dotpart[(long)t * n + rw];
         yr += x.re;
         yi += x.im;
       }
-      for (int p = sub; p <= pr; p += 4) {
+      for (int p = sub; p <= pr; p += S) {
         const cplx x = q.part[(long)p * n + rw];
         yr += x.re;
         yi += x.im;
@@ -482,18 +483,18 @@ __global__ __launch_bounds__(4 * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W
       yr = ycols[rw].re;
       yi = ycols[rw].im;
     }
-    for (int t = sub; t < r; t += 4) {
+    for (int t = sub; t < r; t += S) {
       const cplx a = cmul(q.X[rw + (long)t * n], zs[t]), c = cmul(q.X[rw + (long)(jp + t) * n], zs[r + t]);
       yr -= a.re + c.re;
       yi -= a.im + c.im;
     }
-    for (int m = 1; m < 4; m <<= 1) {
+    for (int m = 1; m < S; m <<= 1) {
       yr += __shfl_xor(yr, m, 64);
       yi += __shfl_xor(yi, m, 64);
     }
     return cplx{yr, yi};
   };
-  if (tid < 4) {
+  if (tid < S) {
     const cplx yk = tp != 0.0 ? y_at(k) : cplx{0.0, 0.0};
     if (tid == 0) sh_yk = yk;
   }
@@ -513,13 +514,13 @@ __global__ __launch_bounds__(4 * TRD_PANEL_ROWS) void trd_panel_kernel(EigWork W
   if (with_col) {
     cplx *col = W.A + (long)b * n * n + (long)k * n;
     double sr = 0.0, si = 0.0;
-    for (int t = sub; t < r; t += 4) {
+    for (int t = sub; t < r; t += S) {
       const cplx vi = q.X[row + (long)t * n], wi = q.X[row + (long)(jp + t) * n];
       const cplx vk = rowk[t], wk = rowk[r + t];
       sr += (vi.re * wk.re + vi.im * wk.im) + (wi.re * vk.re + wi.im * vk.im);
       si += (vi.im * wk.re - vi.re * wk.im) + (wi.im * vk.re - wi.re * vk.im);
     }
-    for (int m = 1; m < 4; m <<= 1) {
+    for (int m = 1; m < S; m <<= 1) {
       sr += __shfl_xor(sr, m, 64);
       si += __shfl_xor(si, m, 64);
     }
@@ -559,14 +560,15 @@ __global__ __launch_bounds__(NT) void trd_reflect_kernel(EigWork W, int n, int k
     const int r = j - 1;
     const double tp = W.tau[2 * b + ((k - 1) & 1)];
     cplx K{0.0, 0.0};
-    if (tp != 0.0) {
+    if (tp != 0.0) {  // the row pass's partial sums, reduced in a fixed order
       const int nch = (n - k + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS;
-      for (int c = 0; c < nch; ++c) {  // fixed order
-        K.re += q.kpart[c].re;
-        K.im += q.kpart[c].im;
+      double kr = 0.0, ki = 0.0;
+      for (int c = tid; c < nch; c += NT) {
+        kr += q.kpart[c].re;
+        ki += q.kpart[c].im;
       }
-      K.re *= 0.5 * tp * tp;
-      K.im *= 0.5 * tp * tp;
+      K.re = 0.5 * tp * tp * block_sum_nt<NT>(kr, red);
+      K.im = 0.5 * tp * tp * block_sum_nt<NT>(ki, red);
     }
     two_kr = 2.0 * K.re;
     const cplx *y = W.v + (long)b * 2 * n;
@@ -739,7 +741,8 @@ hipError_t tridiagonalize_blocked(const EigWork &w, int n, int B, hipStream_t s)
         const int rows = n - (k0 + j);
         const int tiled = rows >= TRD_TILED_MIN ? 1 : 0;  // the form of A v for reflector j - 1 (m = rows)
         hipLaunchKernelGGL(trd_panel_kernel, dim3((unsigned)((rows + TRD_PANEL_ROWS - 1) / TRD_PANEL_ROWS), B),
-                           dim3(4 * TRD_PANEL_ROWS), 0, s, w, n, k0, jp, j - 1, j < jp ? 1 : 0, tiled);
+                           dim3(TRD_PANEL_TPR * TRD_PANEL_ROWS), 0, s, w, n, k0, jp, j - 1, j < jp ? 1 : 0,
+                           tiled);
       }
       hipLaunchKernelGGL(trd_reflect_kernel<TRD_REFLECT_THREADS>, one, rt, 0, s, w, n, k0, jp, j);
       if ((err = hipGetLastError()) != hipSuccess) return err;

@@ -250,10 +250,10 @@ constexpr int TRD_NB = 32;
 constexpr int TRD_BLOCKED_MIN = 512;
 constexpr double TRD_BLOCKED_WORK = 16777216.0;
 // Complex entries of the blocked reduction's per-matrix storage: X and Y (n x 2 TRD_NB each),
-// 16 row chunks of z partial sums (2 TRD_NB each), one v^+ y partial per 64 rows, and the row
+// 16 row chunks of z partial sums (2 TRD_NB each), one v^+ y partial per 32 rows, and the row
 // and column sums of A v per 64 x 64 tile (two n-vectors per tile row or column).
 inline long trd_panel_elems(int n) {
-  return (long)4 * TRD_NB * n + 16L * 2 * TRD_NB + (n + 63) / 64 + 2L * ((n + 63) / 64) * n;
+  return (long)4 * TRD_NB * n + 16L * 2 * TRD_NB + (n + 31) / 32 + 2L * ((n + 63) / 64) * n;
 }
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,
                        int *n_out, hipStream_t s);
