@@ -562,7 +562,7 @@ __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
     return;
   }
   __shared__ double sh_tau, sh_pc, red[NW];
-  __shared__ int sh_j, sh_w, sh_out;
+  __shared__ int sh_j, sh_w;
   __shared__ cplx sh_q[2 * BLOCK_KMAX], sh_gam[BLOCK_KMAX], sh_h[2 * BLOCK_KMAX][2], sh_a[BLOCK_KMAX][2];
   __shared__ double sh_tauh, sh_delta;
   __shared__ cplx sh_c;
@@ -671,7 +671,6 @@ __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
       for (int k = 0; k < N; ++k) x[k] = cplx{0.0, 0.0};
     }
     const int outcome = (sh_pc <= p) ? 1 : 0;
-    sh_out = outcome;
     sh_tauh = tau_h;
     if (outcome == 1) {
       sh_delta = -1.0;

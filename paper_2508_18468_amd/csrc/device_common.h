@@ -234,7 +234,7 @@ __device__ int pm_measure_block(cplx *Ub, int L, int N, double q, uint64_t seed,
 __device__ inline void tridiag_body(cplx *A, int ld, int n, cplx *v, cplx *p, double *d, double *e,
                              double *red) {
   const int tid = threadIdx.x;
-  __shared__ double s_tau, s_kr, s_ki;
+  __shared__ double s_tau;
   __shared__ int s_skip;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
