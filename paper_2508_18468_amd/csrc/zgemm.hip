@@ -18,8 +18,12 @@
 //   128 x 128, 8 waves, 64 x 32 per wave   the large ones: half the L2->CU
 //              bytes per flop of the small tile, 64 accumulator doubles per
 //              lane (more per wave would overflow the register file).
-// K advances in chunks of 16 through double-buffered LDS; the next chunk is
-// fetched into registers while the current one feeds the matrix cores.
+// K advances in chunks of 16 through one LDS buffer; the next chunk is fetched
+// into registers while the current one feeds the matrix cores, then stored
+// between two barriers.  A single buffer (66 KiB for 128 x 128 tiles) lets two
+// workgroups share a compute unit, one computing while the other waits at a
+// barrier; the reduction epilogues, which reuse the operand LDS as scratch, keep
+// two buffers.
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher hands workgroup i to
 // XCD i mod 8, so the 1-D grid is ordered such that all tiles of one batch
@@ -198,8 +202,9 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   if (g.aUpper) kbeg = (m0 / KT) * KT;
   if (g.bUpper) kend = min(g.K, n0 + NT);
 
-  __shared__ double Ar[2][KT][MT + PAD], Ai[2][KT][MT + PAD];
-  __shared__ double Br[2][KT][NT + PAD], Bi[2][KT][NT + PAD];
+  constexpr int NBUF = (FL & (FL_SQSUM | FL_DIAG)) != 0 ? 2 : 1;
+  __shared__ double Ar[NBUF][KT][MT + PAD], Ai[NBUF][KT][MT + PAD];
+  __shared__ double Br[NBUF][KT][NT + PAD], Bi[NBUF][KT][NT + PAD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave % WM, wc = wave / WM;
@@ -294,7 +299,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
     __syncthreads();
   }
   for (int it = 0; it < nk; ++it) {
-    const int buf = it & 1;
+    const int buf = NBUF == 2 ? (it & 1) : 0;
     if (it + 1 < nk) load(kbeg + (it + 1) * KT);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
@@ -329,7 +334,8 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
         }
       }
     }
-    if (it + 1 < nk) store(buf ^ 1);
+    if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
+    if (it + 1 < nk) store(NBUF == 2 ? (buf ^ 1) : 0);
     __syncthreads();
   }
 
