@@ -221,3 +221,25 @@ def test_known_spectrum_with_tiny_couplings_blocked():
         err = float(np.max(np.abs(np.sort(got[t]) - np.sort(lams[t]))))
         assert err <= 200 * len(region) * EPS, (t, err)
     sim.close()
+
+
+def test_known_spectrum_blocked_tiled_batch():
+    """14 trajectories, L=2200, N=1100, a random region of 1100 sites: the blocked reduction with
+    the tiled lower-triangle A v for trailing blocks of 1024 and more (ragged 64 x 64 tiles), then
+    whole columns, a ragged last panel and the LDS tail; every spectrum and entropy against its
+    known spectrum."""
+    L, N, B, l = 2200, 1100, 14, 1100
+    rng = np.random.default_rng(51)
+    region = sorted(rng.choice(L, l, replace=False).tolist())
+    lams = [spectrum_mix(l, rng) for _ in range(B)]
+    U = np.concatenate([known_state(L, N, region, lam, rng) for lam in lams])
+    sim = make_sim(1, L, n_traj=B)
+    sim.set_state(U, 0)
+    got = sim.region_spectrum(region)
+    S = sim.entropy(region)
+    delta = 200 * l * EPS
+    for t in range(B):
+        err = float(np.max(np.abs(np.sort(got[t]) - np.sort(lams[t]))))
+        assert err <= delta, (t, err)
+        assert abs(S[t] - h(lams[t]).sum()) <= entropy_bound(lams[t], delta)
+    sim.close()
