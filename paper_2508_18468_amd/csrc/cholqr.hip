@@ -132,8 +132,9 @@ GemmDesc desc() {
 }
 
 // One pass: Uout = Uin R^{-1}.  near_identity (pass 2): Uout is not written when the Gram
-// certifies Uin (max |G - I| <= CHOL_KEEP_MAX, left in wk.dev).
-hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &wk,
+// certifies Uin (max |G - I| <= CHOL_KEEP_MAX, left in wk.dev).  Otherwise Uin may be
+// overwritten (pass 1 solves its right block in place).
+hipError_t cholqr_pass(cplx *Uin, cplx *Uout, int L, int N, int B, const CholWork &wk,
                        bool near_identity, hipStream_t s) {
   hipError_t e;
   const long NN = (long)N * N;
@@ -197,7 +198,14 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
   // over all its block pairs and all trajectories (T = R11^{-1} R12, then -T R22^{-1}); the
   // last pair of a level may have a narrower right block.  T lives in Uout, which is free
   // until the final product (at most N^2 / 2 <= L N entries per trajectory).
+  // Pass 1 stops below the top level: with R = [R11 R12; 0 R22] split at S_top (the largest
+  // level, S_top < N <= 2 S_top), Q = U R^{-1} is Q1 = U1 R11^{-1}, then U2 -= Q1 R12 in place and
+  // Q2 = U2 R22^{-1}: the same flops as U R^{-1} without forming -R11^{-1} R12 R22^{-1}.
+  const bool split = !near_identity && N > NB;
+  long S_top = NB;
+  while (2 * S_top < N) S_top *= 2;
   for (long S = NB; S < N; S *= 2) {
+    if (split && S == S_top) break;
     const int full = (int)(N / (2 * S));                        // pairs with a complete right block
     const int w2 = (int)(N - (long)full * 2 * S - S);           // right width of a last, narrower pair
     for (int part = 0; part < 2; ++part) {
@@ -228,6 +236,37 @@ hipError_t cholqr_pass(const cplx *Uin, cplx *Uout, int L, int N, int B, const C
         if ((e = zgemm(g, s)) != hipSuccess) return e;
       }
     }
+  }
+  if (split) {
+    const int w1 = (int)S_top, w2 = N - (int)S_top;
+    {  // Q1 = U1 R11^{-1}
+      GemmDesc g = desc();
+      g.M = L; g.N = w1; g.K = w1; g.batch = B;
+      g.A = Uin; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
+      g.B = wk.Rinv; g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;
+      g.D = Uout; g.ldd = L; g.sD = (long)L * N;
+      if ((e = zgemm(g, s)) != hipSuccess) return e;
+    }
+    {  // U2 -= Q1 R12 (each entry reads only itself from U2)
+      GemmDesc g = desc();
+      g.M = L; g.N = w2; g.K = w1; g.batch = B;
+      g.A = Uout; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
+      g.B = wk.G + S_top * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
+      g.Cin = Uin + S_top * L; g.ldcin = L; g.sCin = (long)L * N;
+      g.D = Uin + S_top * L; g.ldd = L; g.sD = (long)L * N;
+      g.alpha = cplx{-1.0, 0.0};
+      g.beta = cplx{1.0, 0.0};
+      if ((e = zgemm(g, s)) != hipSuccess) return e;
+    }
+    {  // Q2 = U2 R22^{-1}
+      GemmDesc g = desc();
+      g.M = L; g.N = w2; g.K = w2; g.batch = B;
+      g.A = Uin + S_top * L; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
+      g.B = wk.Rinv + S_top * ((long)N + 1); g.ldb = N; g.sB = NN; g.opB = OP_N; g.bUpper = 1;
+      g.D = Uout + S_top * L; g.ldd = L; g.sD = (long)L * N;
+      if ((e = zgemm(g, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   // Uout = Uin R^{-1}; in the second pass skipped on the device when Uin is already
   // orthonormal to CHOL_KEEP_MAX
