@@ -534,7 +534,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int BLOCK_KMAX = 64;
-constexpr int BLOCK_EVENT_THREADS = 1024;
+constexpr int BLOCK_EVENT_THREADS = 512;  // two workgroups per compute unit (1024 threads: one, and a second round past 256 trajectories)
 
 template <int NT>
 __global__ __launch_bounds__(NT) void cont_block_event_kernel(BlockArgs a) {
