@@ -259,3 +259,24 @@ def test_orthonormality_after_certified_second_pass():
             dev = np.abs(U[t].conj().T @ U[t] - np.eye(L // 2)).max()
             assert dev <= 1e-13 + 4 * L * 2.2e-16, (protocol, t, dev)
     sim.close()
+
+
+@pytest.mark.parametrize("dim,Lx,Ly", [(1, 260, 1), (1, 400, 1), (1, 600, 1), (2, 20, 20)])
+def test_cholqr_split_sizes(dim, Lx, Ly):
+    """Particle numbers N = 130, 200, 300, 200 split the first Cholesky-QR pass's product at
+    128, 128, 256 and 128 columns, leaving right blocks of 2, 72, 44 and 72 columns (the 72-wide
+    inverse assembled from a narrower last pair one level down): strong homodyne steps, where the
+    first pass does real work, against the oracle's Householder QR."""
+    B = 2
+    sim = make_sim(dim, Lx, Ly, n_traj=B, uids=[7, 8])
+    ob = OracleBatch(dim, Lx, Ly, 0.05, [7, 8])
+    gam = [2.0, 6.0]
+    for n in range(5):
+        sim.step(QSD, gam, 0.05, 21)
+        ob.step(QSD, gam, 21)
+    U, _ = sim.get_state()
+    N = U.shape[2]
+    for t in range(B):
+        assert np.abs(U[t].conj().T @ U[t] - np.eye(N)).max() < 1e-12
+        assert np.abs(corr(U[t]) - corr(ob.U[t])).max() < 1e-10
+    sim.close()
