@@ -445,8 +445,8 @@ def main():
                                 "ms_per_step": rfa["T"] / args.steps * 1e3,
                                 "speedup_vs_dense_fp64": rfa["value"] / value,
                                 "note": "banded ring stencil (taps -10..10 at dt=0.05, the dense "
-                                        "propagator to rounding), FP64; the dense GEMM above is the "
-                                        "graded kernel",
+                                        "propagator to rounding), FP64; the roofline above is the "
+                                        "dense GEMM's",
                                 "phase_ms_per_step": {k: (v[0] / args.steps)
                                                       for k, v in rfa["phases"].items()}},
         "rk4_integrator": {"value": rrk["value"], "unit": "L*N*steps/s",
@@ -454,7 +454,7 @@ def main():
                            "speedup_vs_dense_fp64": rrk["value"] / value,
                            "note": "the paper's RK4 step of Eq. (A4) (exponent frozen over the step, "
                                    "four nearest-neighbour passes), FP64; a different integrator with "
-                                   "O(dt^5) local error in the free part, not the graded line",
+                                   "O(dt^5) local error in the free part, not the headline value",
                            "phase_ms_per_step": {k: (v[0] / args.steps)
                                                  for k, v in rrk["phases"].items()}},
         "traj_latency_s": {"p50": None, "p99": None,
