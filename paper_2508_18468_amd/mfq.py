@@ -511,7 +511,7 @@ class Trajectories:
         mfq_ct_events(self.ctx, g, seed, n_events, t_end, reorth_every)
 
     def set_ct_block(self, block):
-        """Deferred continuous-time events on rings: blocks of `block` events (0: one by one)."""
+        """Deferred continuous-time events (rings and tori): blocks of `block` events (0: one by one)."""
         _check(self.ctx, lib().mfq_set_ct_block(self.ctx, int(block)))
 
     def ct_last_events(self):
