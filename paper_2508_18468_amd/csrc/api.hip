@@ -55,7 +55,7 @@ struct mfq_ctx {
   void *rk_buf = nullptr;   // RK4 scratch (a third state buffer and the diagonal), on first use
   size_t rk_cap = 0;
   bool ct_any = false;  // an event batch has run since mfq_init_state
-  int ct_block = 0;     // deferred events per block on rings (0: event by event)
+  int ct_block = 0;     // deferred continuous-time events per block (0: event by event)
   BlockWork bw{};
   void *blk_buf = nullptr;
   size_t blk_cap = 0;
