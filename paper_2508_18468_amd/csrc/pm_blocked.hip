@@ -16,7 +16,11 @@
 //   2. C_MM on the matrix cores (gathered rows);
 //   3. sequential elimination on C_MM with the outcome decided at each pivot;
 //   4. LQ of the outcome-1 rows X = U_M1 by Householder reflectors from the
-//      right (X Q = [L 0]), reflectors collected into V;
+//      right (X Q = [L 0]), reflectors collected into V, in panels of LQ_PANEL
+//      rows: each panel's reflectors one launch each on the panel's rows only,
+//      then the rows below take the whole panel at once, X <- X (I - V T V^+),
+//      as three GEMMs (X is kept conjugated and row-major, i.e. X^+ column-major,
+//      so the update reads (I - V T^+ V^+) X^+);
 //   5. U <- U Q in compact WY blocks of 64 (U -= (U V T) V^+, three GEMMs);
 //   6. columns 0..k1-1 := e_j (j in M1), measured rows of the other columns := 0.
 // The Cholesky-QR of the step then normalises the columns that lost their
@@ -162,7 +166,10 @@ __global__ __launch_bounds__(256) void pm_split_kernel(const int *sites, const i
   if (tid == 0) k1[b] = total;
 }
 
-// X[r][:] = U[m1[r], :] (row-major, ld = N) for r < k1; grid (rows, trajectories).
+constexpr int LQ_PANEL = 32;  // reflectors per panel of the blocked LQ
+constexpr int LQ_KSPLIT = 16;  // K slices of the panel's short, deep products
+
+// X[r][:] = conj(U[m1[r], :]) (row-major, ld = N) for r < k1; grid (rows, trajectories).
 __global__ __launch_bounds__(256) void pm_gather_kernel(const cplx *U, int L, int N, const int *m1,
                                                         const int *k1, cplx *X, long sX) {
   const int r = blockIdx.x, b = blockIdx.y;
@@ -170,7 +177,10 @@ __global__ __launch_bounds__(256) void pm_gather_kernel(const cplx *U, int L, in
   const cplx *Ub = U + (long)b * L * N;
   const int row = m1[(long)b * L + r];
   cplx *xr = X + (long)b * sX + (long)r * N;
-  for (int c = threadIdx.x; c < N; c += 256) xr[c] = Ub[row + (long)c * L];
+  for (int c = threadIdx.x; c < N; c += 256) {
+    const cplx u = Ub[row + (long)c * L];
+    xr[c] = cplx{u.re, -u.im};
+  }
 }
 
 // Columns k1 .. ncol-1 of V (N x ncol per trajectory, ld = N) set to zero.
@@ -186,60 +196,82 @@ __global__ __launch_bounds__(256) void pm_vpad_kernel(cplx *V, long sV, int N, c
 // scaled by its largest component), so that X[t, :] H is zero past column t.  One wave per row r >= t; every wave forms
 // (v, tau) from row t itself; the wave of row t stores v in column t of V
 // (zero above row t) and tau, the others apply X[r, :] <- X[r, :] H.
-__global__ __launch_bounds__(256) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t,
+// Reflector t of the LQ on X (stored conjugated: Xs = conj(X), row-major), applied to the rows
+// t+1 .. rend-1 (one workgroup per row, every workgroup forming the reflector from row t
+// itself): v = conj(x_t) scaled, H = I - tau v v^+ with x_t H = beta e_t, and x_r <- x_r H,
+// i.e. Xs[r] -= tau conj(s) v with s = x_r v.  Row t writes v into column t of V.
+__global__ __launch_bounds__(256) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t, int rend,
                                                     cplx *V, long sV, double *tau, int L) {
-  const int b = blockIdx.y, lane = threadIdx.x & 63;
-  const int kb = k1[b];
-  const int r = t + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= kb || r >= kb) return;
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int kb = min(k1[b], rend);
+  const int r = t + blockIdx.x;
+  if (t >= k1[b] || r >= kb) return;  // uniform over the workgroup
+  __shared__ double red[4];
   cplx *Xb = X + (long)b * sX;
-  const cplx *xt = Xb + (long)t * N;
-  // z scaled by its largest component (see make_reflector)
+  const cplx *xt = Xb + (long)t * N;  // conj(x_t)
+  // v scaled by its largest component (see make_reflector)
   double mx = 0.0;
-  for (int c = t + lane; c < N; c += 64) mx = fmax(mx, cmax_abs(xt[c]));
-  const double s = wmax(mx);
+  for (int c = t + tid; c < N; c += 256) mx = fmax(mx, cmax_abs(xt[c]));
+  const double s = block_max256(mx, red);
   const double inv = s >= REFLECT_TINY ? 1.0 / s : 0.0;
   double tail = 0.0;
-  for (int c = t + 1 + lane; c < N; c += 64) {
+  for (int c = t + 1 + tid; c < N; c += 256) {
     const double re = xt[c].re * inv, im = xt[c].im * inv;
     tail += re * re + im * im;
   }
-  tail = wsum(tail);
+  tail = block_sum256(tail, red);
   double tt = 0.0;
   cplx v0{0.0, 0.0};
   if (tail > 0.0) {
-    const Reflector h = make_reflector(cplx{xt[t].re * inv, -xt[t].im * inv}, tail, s);
+    const Reflector h = make_reflector(cplx{xt[t].re * inv, xt[t].im * inv}, tail, s);
     v0 = h.v0;
     tt = h.tau;
   }
   if (r == t) {
     cplx *vt = V + (long)b * sV + (long)t * N;
-    for (int c = lane; c < N; c += 64) {
+    for (int c = tid; c < N; c += 256) {
       cplx v{0.0, 0.0};
-      if (tt != 0.0 && c >= t) v = c == t ? v0 : cplx{xt[c].re * inv, -xt[c].im * inv};
+      if (tt != 0.0 && c >= t) v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
       vt[c] = v;
     }
-    if (lane == 0) tau[(long)b * L + t] = tt;
+    if (tid == 0) tau[(long)b * L + t] = tt;
     return;
   }
   if (tt == 0.0) return;
   cplx *xr = Xb + (long)r * N;
-  double sr = 0.0, si = 0.0;  // s = X[r, :] v
-  for (int c = t + lane; c < N; c += 64) {
-    const cplx v = c == t ? v0 : cplx{xt[c].re * inv, -xt[c].im * inv};
+  double sr = 0.0, si = 0.0;  // s = x_r v = sum_c conj(Xs[r, c]) v_c
+  for (int c = t + tid; c < N; c += 256) {
+    const cplx v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
     const cplx x = xr[c];
-    sr += x.re * v.re - x.im * v.im;
-    si += x.re * v.im + x.im * v.re;
+    sr += x.re * v.re + x.im * v.im;
+    si += x.re * v.im - x.im * v.re;
   }
-  sr = wsum(sr) * tt;
-  si = wsum(si) * tt;
-  for (int c = t + lane; c < N; c += 64) {  // X[r, c] -= tau s conj(v_c)
-    const cplx v = c == t ? v0 : cplx{xt[c].re * inv, -xt[c].im * inv};
+  sr = block_sum256(sr, red) * tt;
+  si = block_sum256(si, red) * tt;
+  for (int c = t + tid; c < N; c += 256) {  // Xs[r, c] -= tau conj(s) v_c
+    const cplx v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
     cplx x = xr[c];
     x.re -= sr * v.re + si * v.im;
-    x.im -= si * v.re - sr * v.im;
+    x.im -= sr * v.im - si * v.re;
     xr[c] = x;
   }
+}
+
+// out[b][i] = sum_s part[b][s][i] (i < n) in a fixed order: the K-split partial products of a
+// short, deep product (the panel's V^+ [V X^+], K = N).
+__global__ __launch_bounds__(256) void pm_ksum_kernel(const cplx *part, long sPart, int ks, long n, cplx *out,
+                                                      long sOut) {
+  const int b = blockIdx.y;
+  const long i = blockIdx.x * 256L + threadIdx.x;
+  if (i >= n) return;
+  const cplx *pb = part + (long)b * sPart;
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < ks; ++q) {
+    const cplx x = pb[(long)q * n + i];
+    re += x.re;
+    im += x.im;
+  }
+  out[(long)b * sOut + i] = cplx{re, im};
 }
 
 // Triangular factor of a compact-WY block (columns c0 .. c0+w-1 of V):
@@ -355,12 +387,69 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
     // 4. LQ of the outcome-1 rows: X (row-major k1 x N) in R, reflectors in V = G (N x k1max)
     hipLaunchKernelGGL(pm_gather_kernel, dim3(k1max, B), dim3(256), 0, s, U, L, N, w.m1, w.k1, w.R, NN);
     hipLaunchKernelGGL(pm_vpad_kernel, dim3(k1max, B), dim3(256), 0, s, w.G, NN, N, w.k1, k1max);
-    for (int t = 0; t < k1max; ++t) {
-      const int rows = (k1max - t + 3) / 4;
-      hipLaunchKernelGGL(pm_lq_kernel, dim3(rows, B), dim3(256), 0, s, w.R, NN, N, w.k1, t, w.G, NN,
-                         w.tau, L);
+    // panels of LQ_PANEL reflectors; the rows below a panel take it as X <- X (I - V T V^+) on the
+    // stored X^+ (column-major N x k1max, ld N): Wh = V^+ X^+, Zh = T^+ Wh, X^+ -= V Zh.  Scratch:
+    // the panel's Gram and T after X in R, Wh and Zh in w.T.
+    const bool blocked_lq = k1max > LQ_PANEL && (long)k1max * N + 2L * LQ_PANEL * LQ_PANEL <= NN;
+    const int panel = blocked_lq ? LQ_PANEL : k1max;
+    for (int t0 = 0; t0 < k1max; t0 += panel) {
+      const int t1 = std::min(k1max, t0 + panel);
+      for (int t = t0; t < t1; ++t)
+        hipLaunchKernelGGL(pm_lq_kernel, dim3(t1 - t, B), dim3(256), 0, s, w.R, NN, N, w.k1, t, t1, w.G, NN,
+                           w.tau, L);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int m = k1max - t1, wb = t1 - t0;
+      if (!blocked_lq || m <= 0) continue;
+      const cplx *Vb = w.G + (long)t0 * N;
+      cplx *Gb = w.R + (long)k1max * N, *Tb = Gb + LQ_PANEL * LQ_PANEL;
+      cplx *Wh = w.T, *Zh = w.T + (long)LQ_PANEL * k1max;
+      cplx *Xr = w.R + (long)t1 * N;  // rows t1 .. of X, i.e. columns t1 .. of X^+
+      // Gram V_b^+ V_b and Wh = V_b^+ X^+: short (wb rows) and deep (K = N) products, split over
+      // K into LQ_KSPLIT slices (second batch dimension) and summed in a fixed order; partials in
+      // the idle state buffer
+      const long sPart = (long)L * N;
+      int ks = LQ_KSPLIT;  // slices of at least 128 rows, dividing N, partials within one state
+      while (ks > 1 && (N % ks != 0 || N / ks < 128 || (long)ks * LQ_PANEL * k1max > sPart)) ks /= 2;
+      const int kc = N / ks;
+      for (int which = 0; which < 2; ++which) {
+        const int ncol = which == 0 ? wb : m;
+        const long n = (long)wb * ncol;
+        GemmDesc g = desc();
+        g.M = wb; g.N = ncol; g.K = kc; g.batch = B * ks; g.batch2 = ks;
+        g.A = Vb; g.lda = N; g.sA = NN; g.sA2 = kc; g.opA = OP_C;
+        g.B = which == 0 ? Vb : Xr; g.ldb = N; g.sB = NN; g.sB2 = kc; g.opB = OP_N;
+        g.D = scratch; g.ldd = wb; g.sD = sPart; g.sD2 = n;
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(pm_ksum_kernel, dim3((unsigned)((n + 255) / 256), B), dim3(256), 0, s,
+                           (const cplx *)scratch, sPart, ks, n, which == 0 ? Gb : Wh,
+                           which == 0 ? NN : (long)N * WY);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (which == 0) {
+          hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb, NN, Tb, NN, wb, w.tau, w.k1, t0,
+                             L);
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+      }
+      {  // Zh = T^+ Wh
+        GemmDesc g = desc();
+        g.M = wb; g.N = m; g.K = wb; g.batch = B;
+        g.A = Tb; g.lda = wb; g.sA = NN; g.opA = OP_C;
+        g.B = Wh; g.ldb = wb; g.sB = (long)N * WY; g.opB = OP_N;
+        g.D = Zh; g.ldd = wb; g.sD = (long)N * WY;
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
+      {  // X^+ -= V_b Zh
+        GemmDesc g = desc();
+        g.M = N; g.N = m; g.K = wb; g.batch = B;
+        g.A = Vb; g.lda = N; g.sA = NN; g.opA = OP_N;
+        g.B = Zh; g.ldb = wb; g.sB = (long)N * WY; g.opB = OP_N;
+        g.Cin = Xr; g.ldcin = N; g.sCin = NN;
+        g.D = Xr; g.ldd = N; g.sD = NN;
+        g.alpha = cplx{-1.0, 0.0};
+        g.beta = cplx{1.0, 0.0};
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     // 5. U <- U Q, block by block: Gram V_b^+ V_b and T in R, V_b T in w.T, W = U V_b T in scratch
     for (int c0 = 0; c0 < k1max; c0 += WY) {
       const int wb = std::min(WY, k1max - c0);
