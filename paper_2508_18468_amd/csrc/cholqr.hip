@@ -2,9 +2,10 @@
 //
 // The paper keeps U^+ U = 1 by a QR decomposition after every step
 // (Appendix A).  Here one pass is: Gram G = U^+ U on the matrix cores (upper
-// triangle only), blocked right-looking Cholesky G = R^+ R (upper R, block
-// 64: the diagonal block factorised and inverted in LDS, the block row solved
-// and the trailing matrix updated by the batched GEMM), the triangular
+// triangle only), blocked Cholesky G = R^+ R (upper R, block 64: the diagonal
+// block factorised and inverted in LDS, the block row solved and the later rows
+// updated by the batched GEMM, right-looking inside panels of 512 rows and one
+// rank-512 update of the rest per panel), the triangular
 // inverse R^{-1} assembled block column by block column from GEMMs, and the
 // triangular product U R^{-1} (zero blocks of R^{-1} skipped).  Two passes
 // (Cholesky-QR2) bring U^+ U to identity at working precision for the
@@ -158,34 +159,55 @@ hipError_t cholqr_pass(cplx *Uin, cplx *Uout, int L, int N, int B, const CholWor
     }
     if ((e = zgemm(g, s)) != hipSuccess) return e;
   }
-  const int nJ = (N + NB - 1) / NB;
-  for (int J = 0; J < nJ; ++J) {
-    const int c0 = J * NB, w = std::min(NB, N - c0);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(B), dim3(256), 0, s, wk.G, wk.Rinv, N, c0, w, wk.flag,
-                       skip, thr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int r0 = c0 + w, nr = N - r0;
-    if (nr <= 0) break;
-    // block row: R_J,rest = R_JJ^{-+} G_J,rest (in place; one row tile, so every
-    // workgroup reads its whole column panel before writing it)
-    {
-      GemmDesc g = desc();
-      g.skip_if_le = skip; g.skip_thr = thr;
-      g.M = w; g.N = nr; g.K = w; g.batch = B;
-      g.A = wk.Rinv + c0 + (long)c0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
-      g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
-      g.D = wk.G + c0 + (long)r0 * N; g.ldd = N; g.sD = NN;
-      if ((e = zgemm(g, s)) != hipSuccess) return e;
+  // Two levels: outer panels of CHOL_OUTER rows of R.  Inside a panel, block J (NB rows) is
+  // factorised, its block row solved to the end of the matrix, and only the panel's later block
+  // rows updated (K = NB); the rows below the panel get one update per panel (K = CHOL_OUTER),
+  // which has CHOL_OUTER / NB times the flops per byte of a per-block trailing update.
+  for (int p0 = 0; p0 < N; p0 += CHOL_OUTER) {
+    const int p1 = std::min(N, p0 + CHOL_OUTER);
+    for (int c0 = p0; c0 < p1; c0 += NB) {
+      const int w = std::min(NB, p1 - c0);
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(B), dim3(256), 0, s, wk.G, wk.Rinv, N, c0, w, wk.flag,
+                         skip, thr);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const int r0 = c0 + w, nr = N - r0;
+      if (nr <= 0) break;
+      // block row: R_J,rest = R_JJ^{-+} G_J,rest (in place; one row tile, so every
+      // workgroup reads its whole column panel before writing it)
+      {
+        GemmDesc g = desc();
+        g.skip_if_le = skip; g.skip_thr = thr;
+        g.M = w; g.N = nr; g.K = w; g.batch = B;
+        g.A = wk.Rinv + c0 + (long)c0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
+        g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
+        g.D = wk.G + c0 + (long)r0 * N; g.ldd = N; g.sD = NN;
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
+      // the panel's later block rows: G_r0..p1, r0.. -= R_J,r0..p1^+ R_J,r0.. (upper part)
+      if (r0 < p1) {
+        GemmDesc g = desc();
+        g.skip_if_le = skip; g.skip_thr = thr;
+        g.M = p1 - r0; g.N = nr; g.K = w; g.batch = B;
+        g.A = wk.G + c0 + (long)r0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
+        g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
+        g.Cin = wk.G + r0 + (long)r0 * N; g.ldcin = N; g.sCin = NN;
+        g.D = wk.G + r0 + (long)r0 * N; g.ldd = N; g.sD = NN;
+        g.alpha = cplx{-1.0, 0.0};
+        g.beta = cplx{1.0, 0.0};
+        g.tri = TRI_UPPER;
+        if ((e = zgemm(g, s)) != hipSuccess) return e;
+      }
     }
-    // trailing: G_rest,rest -= R_J,rest^+ R_J,rest (upper)
-    {
+    // below the panel: G_p1..,p1.. -= R_P,p1..^+ R_P,p1.. (upper)
+    const int nr = N - p1;
+    if (nr > 0) {
       GemmDesc g = desc();
       g.skip_if_le = skip; g.skip_thr = thr;
-      g.M = nr; g.N = nr; g.K = w; g.batch = B;
-      g.A = wk.G + c0 + (long)r0 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
-      g.B = wk.G + c0 + (long)r0 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
-      g.Cin = wk.G + r0 + (long)r0 * N; g.ldcin = N; g.sCin = NN;
-      g.D = wk.G + r0 + (long)r0 * N; g.ldd = N; g.sD = NN;
+      g.M = nr; g.N = nr; g.K = p1 - p0; g.batch = B;
+      g.A = wk.G + p0 + (long)p1 * N; g.lda = N; g.sA = NN; g.opA = OP_C;
+      g.B = wk.G + p0 + (long)p1 * N; g.ldb = N; g.sB = NN; g.opB = OP_N;
+      g.Cin = wk.G + p1 + (long)p1 * N; g.ldcin = N; g.sCin = NN;
+      g.D = wk.G + p1 + (long)p1 * N; g.ldd = N; g.sD = NN;
       g.alpha = cplx{-1.0, 0.0};
       g.beta = cplx{1.0, 0.0};
       g.tri = TRI_UPPER;

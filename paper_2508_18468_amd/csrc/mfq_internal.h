@@ -182,6 +182,7 @@ struct CholWork {
   double *dev;   // device scalar: max |G - I| of the latest near-identity check
 };
 constexpr int CHOL_NB = 64;
+constexpr int CHOL_OUTER = 8 * CHOL_NB;  // rows of R per outer panel of the blocked Cholesky
 // Largest |U^+ U - I| entry for which the second pass uses the first-order factor.
 constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
 // Largest |U^+ U - I| entry for which the second pass keeps U as it is: the first pass
