@@ -21,7 +21,8 @@
 //      then the rows below take the whole panel at once, X <- X (I - V T V^+),
 //      as three GEMMs (X is kept conjugated and row-major, i.e. X^+ column-major,
 //      so the update reads (I - V T^+ V^+) X^+);
-//   5. U <- U Q in compact WY blocks of 64 (U -= (U V T) V^+, three GEMMs);
+//   5. U <- U Q in compact WY blocks of 128 where the N x N scratch holds them,
+//      else 64 (U -= (U V T) V^+, three GEMMs; one pass over U per block);
 //   6. columns 0..k1-1 := e_j (j in M1), measured rows of the other columns := 0.
 // The Cholesky-QR of the step then normalises the columns that lost their
 // M0 amplitude.  The host reads the site and outcome-1 counts (two stream
@@ -35,7 +36,8 @@ namespace mfq {
 
 namespace {
 
-constexpr int WY = 64;  // width of a compact-WY block
+constexpr int WY = 64;    // width of a compact-WY block, and of one T-factor launch
+constexpr int WY2 = 128;  // wide compact-WY block: two T factors of WY joined by GEMMs
 
 __device__ __forceinline__ double wsum(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -277,9 +279,10 @@ __global__ __launch_bounds__(256) void pm_ksum_kernel(const cplx *part, long sPa
 // Triangular factor of a compact-WY block (columns c0 .. c0+w-1 of V):
 // H_c0 ... H_c0+w-1 = I - V_b T V_b^+, T upper triangular with T_tt = tau_t and
 // T[0:t, t] = -tau_t T[0:t, 0:t] (V_b^+ V_b)[0:t, t].  Thread i owns row i of T
-// (row i of T depends only on row i and the Gram), so no barriers are needed.
-__global__ __launch_bounds__(64) void pm_tfactor_kernel(const cplx *Gb, long sG, cplx *T, long sT,
-                                                        int w, const double *tau, const int *k1,
+// (row i of T depends only on row i and the Gram), so no barriers are needed.  G and T
+// have leading dimensions ldg and ldt (sub-blocks of a wider block's Gram and T).
+__global__ __launch_bounds__(64) void pm_tfactor_kernel(const cplx *Gb, long sG, int ldg, cplx *T, long sT,
+                                                        int ldt, int w, const double *tau, const int *k1,
                                                         int c0, int L) {
   const int b = blockIdx.x, i = threadIdx.x;
   if (i >= w) return;
@@ -292,7 +295,7 @@ __global__ __launch_bounds__(64) void pm_tfactor_kernel(const cplx *Gb, long sG,
     if (i < t) {
       double sr = 0.0, si = 0.0;
       for (int l = i; l < t; ++l) {
-        const cplx a = Tb[i + (long)l * w], g = G[l + (long)t * w];
+        const cplx a = Tb[i + (long)l * ldt], g = G[l + (long)t * ldg];
         sr += a.re * g.re - a.im * g.im;
         si += a.re * g.im + a.im * g.re;
       }
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(64) void pm_tfactor_kernel(const cplx *Gb, long sG,
     } else if (i == t) {
       out = cplx{tt, 0.0};
     }
-    Tb[i + (long)t * w] = out;
+    Tb[i + (long)t * ldt] = out;
   }
 }
 
@@ -425,8 +428,8 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
                            which == 0 ? NN : (long)N * WY);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (which == 0) {
-          hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb, NN, Tb, NN, wb, w.tau, w.k1, t0,
-                             L);
+          hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb, NN, wb, Tb, NN, wb, wb, w.tau,
+                             w.k1, t0, L);
           if ((e = hipGetLastError()) != hipSuccess) return e;
         }
       }
@@ -450,12 +453,19 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
         if ((e = zgemm(g, s)) != hipSuccess) return e;
       }
     }
-    // 5. U <- U Q, block by block: Gram V_b^+ V_b and T in R, V_b T in w.T, W = U V_b T in scratch
-    for (int c0 = 0; c0 < k1max; c0 += WY) {
-      const int wb = std::min(WY, k1max - c0);
+    // 5. U <- U Q, block by block.  In R: the Gram V_b^+ V_b and T (wb x wb each), then, for
+    // blocks of WY2, V_b T (N x wb); for blocks of WY, V_b T in w.T.  W = U V_b T in scratch.
+    // A block of WY2 columns takes T = [T1, -T1 G12 T2; 0, T2] from the T factors of its two
+    // halves (G12: the Gram's off-diagonal block; -T1 G12 T2 via G12 T2 in w.T).
+    const int wy = 2L * WY2 * WY2 + (long)N * WY2 <= NN ? WY2 : WY;
+    for (int c0 = 0; c0 < k1max; c0 += wy) {
+      const int wb = std::min(wy, k1max - c0);
+      const int w1 = std::min(WY, wb), w2 = wb - w1;
       const cplx *Vb = w.G + (long)c0 * N;
       cplx *Gb = w.R;
-      cplx *Tb = w.R + (long)WY * WY;
+      cplx *Tb = w.R + (long)wy * wy;
+      cplx *VT = wy == WY2 ? w.R + 2L * WY2 * WY2 : w.T;
+      const long sVT = wy == WY2 ? NN : (long)N * WY;
       {
         GemmDesc g = desc();
         g.M = wb; g.N = wb; g.K = N; g.batch = B;
@@ -464,21 +474,51 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
         g.D = Gb; g.ldd = wb; g.sD = NN;
         if ((e = zgemm(g, s)) != hipSuccess) return e;
       }
-      hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb, NN, Tb, NN, wb, w.tau, w.k1,
+      hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb, NN, wb, Tb, NN, wb, w1, w.tau, w.k1,
                          c0, L);
-      {
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (w2 > 0) {
+        const long d2 = w1 + (long)w1 * wb;  // offset of the second half's diagonal block
+        hipLaunchKernelGGL(pm_tfactor_kernel, dim3(B), dim3(64), 0, s, Gb + d2, NN, wb, Tb + d2, NN, wb, w2,
+                           w.tau, w.k1, c0 + w1, L);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        {  // G12 T2 (w1 x w2) in w.T
+          GemmDesc g = desc();
+          g.M = w1; g.N = w2; g.K = w2; g.batch = B;
+          g.A = Gb + (long)w1 * wb; g.lda = wb; g.sA = NN; g.opA = OP_N;
+          g.B = Tb + d2; g.ldb = wb; g.sB = NN; g.opB = OP_N;
+          g.D = w.T; g.ldd = w1; g.sD = (long)N * WY;
+          if ((e = zgemm(g, s)) != hipSuccess) return e;
+        }
+        {  // T12 = -T1 (G12 T2)
+          GemmDesc g = desc();
+          g.M = w1; g.N = w2; g.K = w1; g.batch = B;
+          g.A = Tb; g.lda = wb; g.sA = NN; g.opA = OP_N;
+          g.B = w.T; g.ldb = w1; g.sB = (long)N * WY; g.opB = OP_N;
+          g.D = Tb + (long)w1 * wb; g.ldd = wb; g.sD = NN;
+          g.alpha = cplx{-1.0, 0.0};
+          if ((e = zgemm(g, s)) != hipSuccess) return e;
+        }
+      }
+      {  // V_b T: the first w1 columns are V_1 T1, the rest V_b [T12; T2]
         GemmDesc g = desc();
-        g.M = N; g.N = wb; g.K = wb; g.batch = B;
+        g.M = N; g.N = w1; g.K = w1; g.batch = B;
         g.A = Vb; g.lda = N; g.sA = NN; g.opA = OP_N;
         g.B = Tb; g.ldb = wb; g.sB = NN; g.opB = OP_N;
-        g.D = w.T; g.ldd = N; g.sD = (long)N * WY;
+        g.D = VT; g.ldd = N; g.sD = sVT;
         if ((e = zgemm(g, s)) != hipSuccess) return e;
+        if (w2 > 0) {
+          g.N = w2; g.K = wb;
+          g.B = Tb + (long)w1 * wb;
+          g.D = VT + (long)w1 * N;
+          if ((e = zgemm(g, s)) != hipSuccess) return e;
+        }
       }
       {
         GemmDesc g = desc();
         g.M = L; g.N = wb; g.K = N; g.batch = B;
         g.A = U; g.lda = L; g.sA = (long)L * N; g.opA = OP_N;
-        g.B = w.T; g.ldb = N; g.sB = (long)N * WY; g.opB = OP_N;
+        g.B = VT; g.ldb = N; g.sB = sVT; g.opB = OP_N;
         g.D = scratch; g.ldd = L; g.sD = (long)L * N;
         if ((e = zgemm(g, s)) != hipSuccess) return e;
       }

@@ -70,12 +70,15 @@ def test_blocked_matches_oracle(L, gamma, n_steps):
     sim.close()
 
 
-def test_blocked_equals_workgroup_form():
-    """Same trajectories through both forms: identical events, equal correlation matrices."""
+@pytest.mark.parametrize("gams", [[2.0, 0.7], [9.0, 5.0]])
+def test_blocked_equals_workgroup_form(gams):
+    """Same trajectories through both forms: identical events, equal correlation matrices.
+    L = 640 (N = 320); at rates 9 and 5 a step has more than 64 outcomes 1, so the update of U
+    runs in 128-wide compact-WY blocks whose T joins two 64-wide factors."""
     from paper_2508_18468_amd import mfq
     L, dt, seed = 640, 0.05, 11
     uids = [0, 1]
-    gams = [2.0, 0.7]
+    k1_max = 0
     a = make_sim(1, L, n_traj=2, uids=uids)
     a.set_pm_path(mfq.PM_WORKGROUP)
     b = _blocked(make_sim(1, L, n_traj=2, uids=uids))
@@ -85,6 +88,7 @@ def test_blocked_equals_workgroup_form():
         ea, eb = a.pm_events(), b.pm_events()
         for t in range(2):
             assert [(e[0], e[2]) for e in ea[t]] == [(e[0], e[2]) for e in eb[t]]
+            k1_max = max(k1_max, sum(1 for e in eb[t] if e[2] == 1))
             for x, y, tol in zip(ea[t], eb[t], prob_tols(ea[t])):
                 assert abs(x[1] - y[1]) <= tol, (n, t, x, y, tol)
     Ua, _ = a.get_state()
@@ -93,6 +97,8 @@ def test_blocked_equals_workgroup_form():
         assert np.abs(corr(Ua[t]) - corr(Ub[t])).max() <= 1e-10
     r = list(range(200))
     assert np.abs(a.entropy(r) - b.entropy(r)).max() <= 1e-10
+    if gams[0] > 5.0:
+        assert k1_max > 64
     a.close()
     b.close()
 
