@@ -33,7 +33,7 @@ def test_propagator_bessel_entries():
         ref = (-1j) ** n * special.jv(n, 2 * dt)
         assert abs(P[n, 0] - ref) < 1e-16 + 1e-13 * abs(ref)
         assert abs(P[0, n] - ref) < 1e-16 + 1e-13 * abs(ref)
-    # survey probe values |P_{0,n}| at dt = 0.05
+    # |P_{0,1}| = J_1(0.1) at dt = 0.05, to ten digits
     assert abs(abs(P[0, 1]) - 0.0499375260) < 1e-9
 
 
