@@ -261,12 +261,15 @@ def test_orthonormality_after_certified_second_pass():
     sim.close()
 
 
-@pytest.mark.parametrize("dim,Lx,Ly", [(1, 260, 1), (1, 400, 1), (1, 600, 1), (2, 20, 20)])
+@pytest.mark.parametrize("dim,Lx,Ly", [(1, 260, 1), (1, 400, 1), (1, 600, 1), (2, 20, 20),
+                                       (1, 1100, 1)])
 def test_cholqr_split_sizes(dim, Lx, Ly):
-    """Particle numbers N = 130, 200, 300, 200 split the first Cholesky-QR pass's product at
-    128, 128, 256 and 128 columns, leaving right blocks of 2, 72, 44 and 72 columns (the 72-wide
-    inverse assembled from a narrower last pair one level down): strong homodyne steps, where the
-    first pass does real work, against the oracle's Householder QR."""
+    """Particle numbers N = 130, 200, 300, 200, 550 split the first Cholesky-QR pass's product at
+    128, 128, 256, 128 and 512 columns, leaving right blocks of 2, 72, 44, 72 and 38 columns (the
+    72-wide inverse assembled from a narrower last pair one level down); at N = 550 the Cholesky
+    runs in two outer panels (512 rows, the rank-512 update of the last 38, a 38-row panel):
+    strong homodyne steps, where the first pass does real work, against the oracle's
+    Householder QR."""
     B = 2
     sim = make_sim(dim, Lx, Ly, n_traj=B, uids=[7, 8])
     ob = OracleBatch(dim, Lx, Ly, 0.05, [7, 8])
