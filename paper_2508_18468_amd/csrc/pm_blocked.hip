@@ -169,6 +169,7 @@ __global__ __launch_bounds__(256) void pm_split_kernel(const int *sites, const i
 }
 
 constexpr int LQ_PANEL = 32;  // reflectors per panel of the blocked LQ
+constexpr int LQ_THREADS = 1024;  // one workgroup per row: few rows per launch, long rows
 constexpr int LQ_KSPLIT = 16;  // K slices of the panel's short, deep products
 
 // X[r][:] = conj(U[m1[r], :]) (row-major, ld = N) for r < k1; grid (rows, trajectories).
@@ -202,26 +203,26 @@ __global__ __launch_bounds__(256) void pm_vpad_kernel(cplx *V, long sV, int N, c
 // t+1 .. rend-1 (one workgroup per row, every workgroup forming the reflector from row t
 // itself): v = conj(x_t) scaled, H = I - tau v v^+ with x_t H = beta e_t, and x_r <- x_r H,
 // i.e. Xs[r] -= tau conj(s) v with s = x_r v.  Row t writes v into column t of V.
-__global__ __launch_bounds__(256) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t, int rend,
+__global__ __launch_bounds__(LQ_THREADS) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t, int rend,
                                                     cplx *V, long sV, double *tau, int L) {
   const int b = blockIdx.y, tid = threadIdx.x;
   const int kb = min(k1[b], rend);
   const int r = t + blockIdx.x;
   if (t >= k1[b] || r >= kb) return;  // uniform over the workgroup
-  __shared__ double red[4];
+  __shared__ double red[LQ_THREADS / 64];
   cplx *Xb = X + (long)b * sX;
   const cplx *xt = Xb + (long)t * N;  // conj(x_t)
   // v scaled by its largest component (see make_reflector)
   double mx = 0.0;
-  for (int c = t + tid; c < N; c += 256) mx = fmax(mx, cmax_abs(xt[c]));
-  const double s = block_max256(mx, red);
+  for (int c = t + tid; c < N; c += LQ_THREADS) mx = fmax(mx, cmax_abs(xt[c]));
+  const double s = block_max_nt<LQ_THREADS>(mx, red);
   const double inv = s >= REFLECT_TINY ? 1.0 / s : 0.0;
   double tail = 0.0;
-  for (int c = t + 1 + tid; c < N; c += 256) {
+  for (int c = t + 1 + tid; c < N; c += LQ_THREADS) {
     const double re = xt[c].re * inv, im = xt[c].im * inv;
     tail += re * re + im * im;
   }
-  tail = block_sum256(tail, red);
+  tail = block_sum_nt<LQ_THREADS>(tail, red);
   double tt = 0.0;
   cplx v0{0.0, 0.0};
   if (tail > 0.0) {
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void pm_lq_kernel(cplx *X, long sX, int N, con
   }
   if (r == t) {
     cplx *vt = V + (long)b * sV + (long)t * N;
-    for (int c = tid; c < N; c += 256) {
+    for (int c = tid; c < N; c += LQ_THREADS) {
       cplx v{0.0, 0.0};
       if (tt != 0.0 && c >= t) v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
       vt[c] = v;
@@ -242,15 +243,15 @@ __global__ __launch_bounds__(256) void pm_lq_kernel(cplx *X, long sX, int N, con
   if (tt == 0.0) return;
   cplx *xr = Xb + (long)r * N;
   double sr = 0.0, si = 0.0;  // s = x_r v = sum_c conj(Xs[r, c]) v_c
-  for (int c = t + tid; c < N; c += 256) {
+  for (int c = t + tid; c < N; c += LQ_THREADS) {
     const cplx v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
     const cplx x = xr[c];
     sr += x.re * v.re + x.im * v.im;
     si += x.re * v.im - x.im * v.re;
   }
-  sr = block_sum256(sr, red) * tt;
-  si = block_sum256(si, red) * tt;
-  for (int c = t + tid; c < N; c += 256) {  // Xs[r, c] -= tau conj(s) v_c
+  sr = block_sum_nt<LQ_THREADS>(sr, red) * tt;
+  si = block_sum_nt<LQ_THREADS>(si, red) * tt;
+  for (int c = t + tid; c < N; c += LQ_THREADS) {  // Xs[r, c] -= tau conj(s) v_c
     const cplx v = c == t ? v0 : cplx{xt[c].re * inv, xt[c].im * inv};
     cplx x = xr[c];
     x.re -= sr * v.re + si * v.im;
@@ -398,8 +399,8 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
     for (int t0 = 0; t0 < k1max; t0 += panel) {
       const int t1 = std::min(k1max, t0 + panel);
       for (int t = t0; t < t1; ++t)
-        hipLaunchKernelGGL(pm_lq_kernel, dim3(t1 - t, B), dim3(256), 0, s, w.R, NN, N, w.k1, t, t1, w.G, NN,
-                           w.tau, L);
+        hipLaunchKernelGGL(pm_lq_kernel, dim3(t1 - t, B), dim3(LQ_THREADS), 0, s, w.R, NN, N, w.k1, t, t1,
+                           w.G, NN, w.tau, L);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const int m = k1max - t1, wb = t1 - t0;
       if (!blocked_lq || m <= 0) continue;
