@@ -194,17 +194,14 @@ __global__ __launch_bounds__(256) void pm_vpad_kernel(cplx *V, long sV, int N, c
   for (int i = threadIdx.x; i < N; i += 256) vc[i] = cplx{0.0, 0.0};
 }
 
-// Reflector t of the LQ of X (k1 x N, row-major): H = I - tau v v^+ with
-// z = conj(X[t, t:]), v = z - alpha e_0, alpha = -phase(z_0)|z| (formed from z
-// scaled by its largest component), so that X[t, :] H is zero past column t.  One wave per row r >= t; every wave forms
-// (v, tau) from row t itself; the wave of row t stores v in column t of V
-// (zero above row t) and tau, the others apply X[r, :] <- X[r, :] H.
-// Reflector t of the LQ on X (stored conjugated: Xs = conj(X), row-major), applied to the rows
-// t+1 .. rend-1 (one workgroup per row, every workgroup forming the reflector from row t
-// itself): v = conj(x_t) scaled, H = I - tau v v^+ with x_t H = beta e_t, and x_r <- x_r H,
-// i.e. Xs[r] -= tau conj(s) v with s = x_r v.  Row t writes v into column t of V.
-__global__ __launch_bounds__(LQ_THREADS) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t, int rend,
-                                                    cplx *V, long sV, double *tau, int L) {
+// Reflector t of the LQ of X (k1 x N), applied to the rows t+1 .. rend-1.  X is stored
+// conjugated and row-major (Xs = conj(X)).  With z = Xs[t, t:] scaled by its largest component,
+// H = I - tau v v^+, v = z - alpha e_0, alpha = -phase(z_0)|z|, so that x_t H is zero past
+// column t.  One workgroup per row r in t .. rend-1, each forming (v, tau) from row t itself:
+// row t's workgroup writes v into column t of V (zero above row t) and tau, the others apply
+// x_r <- x_r H, i.e. Xs[r] -= tau conj(s) v with s = x_r v.
+__global__ __launch_bounds__(LQ_THREADS) void pm_lq_kernel(cplx *X, long sX, int N, const int *k1, int t,
+                                                           int rend, cplx *V, long sV, double *tau, int L) {
   const int b = blockIdx.y, tid = threadIdx.x;
   const int kb = min(k1[b], rend);
   const int r = t + blockIdx.x;
