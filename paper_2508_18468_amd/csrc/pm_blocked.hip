@@ -170,9 +170,10 @@ __global__ __launch_bounds__(256) void pm_split_kernel(const int *sites, const i
 
 constexpr int LQ_PANEL = 32;  // reflectors per panel of the blocked LQ
 constexpr int LQ_THREADS = 1024;  // one workgroup per row: few rows per launch, long rows
-constexpr int LQ_KSPLIT = 16;  // K slices of the panel's short, deep products
+constexpr int LQ_KSPLIT = 16;  // K slices of the short, deep products (C_MM, the LQ panel's)
 
 // X[r][:] = conj(U[m1[r], :]) (row-major, ld = N) for r < k1; grid (rows, trajectories).
+// Used for the measured rows (m1 = sites, k1 = counts) and for the outcome-1 rows.
 __global__ __launch_bounds__(256) void pm_gather_kernel(const cplx *U, int L, int N, const int *m1,
                                                         const int *k1, cplx *X, long sX) {
   const int r = blockIdx.x, b = blockIdx.y;
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(LQ_THREADS) void pm_lq_kernel(cplx *X, long sX, int
 }
 
 // out[b][i] = sum_s part[b][s][i] (i < n) in a fixed order: the K-split partial products of a
-// short, deep product (the panel's V^+ [V X^+], K = N).
+// short, deep product (C_MM, the LQ panel's V^+ [V X^+]; K = N).
 __global__ __launch_bounds__(256) void pm_ksum_kernel(const cplx *part, long sPart, int ks, long n, cplx *out,
                                                       long sOut) {
   const int b = blockIdx.y;
@@ -357,14 +358,28 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
     *fallback = true;
     return hipSuccess;
   }
-  // 2. C_MM = U_M U_M^+ into G (ld kmax)
+  // 2. C_MM = U_M U_M^+ into G (ld kmax): the measured rows gathered, conjugated, into R
+  // (Y = U_M^+, N x kmax, ld N), then C_MM = Y^+ Y, a short (kmax rows) and deep (K = N)
+  // product split over K into slices summed in a fixed order, partials in the idle state buffer
+  // (rows past a trajectory's count are left unwritten: they reach only C_MM entries that the
+  // elimination does not read)
   {
+    hipLaunchKernelGGL(pm_gather_kernel, dim3(kmax, B), dim3(256), 0, s, U, L, N, w.sites, w.counts, w.R,
+                       NN);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const long sPart = (long)L * N, n = (long)kmax * kmax;
+    int ks = LQ_KSPLIT;  // slices of at least 128 rows, dividing N, partials within one state
+    while (ks > 1 && (N % ks != 0 || N / ks < 128 || ks * n > sPart)) ks /= 2;
+    const int kc = N / ks;
     GemmDesc g = desc();
-    g.M = kmax; g.N = kmax; g.K = N; g.batch = B;
-    g.A = U; g.lda = L; g.sA = (long)L * N; g.opA = OP_N; g.idxA = w.sites; g.sIdxA = L;
-    g.B = U; g.ldb = L; g.sB = (long)L * N; g.opB = OP_C; g.idxB = w.sites; g.sIdxB = L;
-    g.D = w.G; g.ldd = kmax; g.sD = NN;
+    g.M = kmax; g.N = kmax; g.K = kc; g.batch = B * ks; g.batch2 = ks;
+    g.A = w.R; g.lda = N; g.sA = NN; g.sA2 = kc; g.opA = OP_C;
+    g.B = w.R; g.ldb = N; g.sB = NN; g.sB2 = kc; g.opB = OP_N;
+    g.D = scratch; g.ldd = kmax; g.sD = sPart; g.sD2 = n;
     if ((e = zgemm(g, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(pm_ksum_kernel, dim3((unsigned)((n + 255) / 256), B), dim3(256), 0, s,
+                       (const cplx *)scratch, sPart, ks, n, w.G, NN);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // 3. elimination with the outcome decided at each pivot
   for (int t = 0; t < kmax; ++t) {
