@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -44,6 +45,7 @@ struct mfq_ctx {
   double *p = nullptr, *gamma = nullptr;
   uint64_t *uid = nullptr;
   int *occ = nullptr, *region = nullptr, *flag = nullptr;
+  BreakdownInfo *info = nullptr;  // where the flag's breakdown was seen
   int *pm_sites = nullptr, *pm_out = nullptr, *pm_cnt = nullptr;
   double *pm_prob = nullptr;
   cplx *pm_v = nullptr, *pm_w = nullptr;
@@ -117,85 +119,41 @@ int lattice_L(const mfq_lattice *lat) { return lat->dim == 1 ? lat->Lx : lat->Lx
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Byte layout of the workspace; `base` may be null (sizing only).
-struct Plan {
-  size_t off = 0;
-  char *base = nullptr;
-  template <class T>
-  T *take(size_t count) {
-    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
-    off = align_up(off + count * sizeof(T));
-    return p;
-  }
-};
+// Sub-buffers of the workspace at `base` (256-aligned), from the layout of workspace_layout.h.
+void carve(char *base, const WsLayout &w, const mfq_lattice &lat, int N, mfq_ctx *c) {
+  auto at = [&](int r) -> void * { return w.count[r] ? base + w.off[r] : nullptr; };
+  const long NN = (long)N * N;
+  cplx *G = (cplx *)at(WS_G), *Rinv = (cplx *)at(WS_RINV), *T = (cplx *)at(WS_T);
+  c->Pr32 = (float *)at(WS_PR32); c->Pi32 = (float *)at(WS_PI32);
+  c->X[0] = (cplx *)at(WS_X0); c->X[1] = (cplx *)at(WS_X1); c->P = (cplx *)at(WS_P);
+  c->gx = (cplx *)at(WS_GX); c->gy = (cplx *)at(WS_GY);
+  c->Pkx = (cplx *)at(WS_PKX); c->Pky = (cplx *)at(WS_PKY);
+  c->flag = (int *)at(WS_FLAG);
+  c->info = (BreakdownInfo *)at(WS_INFO);
+  c->chol = CholWork{G, Rinv, T, c->flag, c->info, (double *)at(WS_DEV)};
+  c->step_dev = (int64_t *)at(WS_STEP);
+  c->step_base = (int64_t *)at(WS_STEP_BASE);
+  // the blocked reduction keeps its panels in Rinv (free outside a step; trd_panel_elems(n) <= N^2
+  // for TRD_BLOCKED_MIN <= n <= N)
+  c->eig = EigWork{G, (cplx *)at(WS_EV), (cplx *)at(WS_EW), (cplx *)at(WS_EP), (double *)at(WS_ETAU),
+                   (double *)at(WS_ED), (double *)at(WS_EE), (double *)at(WS_ELAM), (double *)at(WS_ES),
+                   Rinv, NN};
+  c->p = (double *)at(WS_BORN); c->gamma = (double *)at(WS_GAMMA); c->uid = (uint64_t *)at(WS_UID);
+  c->occ = (int *)at(WS_OCC); c->region = (int *)at(WS_REGION);
+  c->pm_sites = (int *)at(WS_PM_SITES); c->pm_out = (int *)at(WS_PM_OUT); c->pm_cnt = (int *)at(WS_PM_CNT);
+  c->pm_prob = (double *)at(WS_PM_PROB);
+  c->pm_v = (cplx *)at(WS_PM_V); c->pm_w = (cplx *)at(WS_PM_W);
+  c->pmb = PmBlockedWork{c->pm_sites, c->pm_out, c->pm_cnt, c->pm_prob, (double *)at(WS_PM_U),
+                         (double *)at(WS_PM_TAU), (int *)at(WS_PM_M1), (int *)at(WS_PM_K1),
+                         (int *)at(WS_PM_CODE), G, Rinv, T};
+  const int Lyr = lat.dim == 2 ? lat.Ly : 1;
+  c->ct = ContWork{(double *)at(WS_CT_T), (cplx *)at(WS_CT_G), (double *)at(WS_CT_JN), (int *)at(WS_CT_INFO),
+                   (double *)at(WS_CT_DINFO), (cplx *)at(WS_CT_V), (cplx *)at(WS_CT_Y), (cplx *)at(WS_CT_YP),
+                   cont_jcap(lat.Lx, Lyr)};
+}
 
-void carve(Plan &pl, const mfq_lattice &lat, int L, int N, int B, int precision, mfq_ctx *c) {
-  const size_t LN = (size_t)L * N, NN = (size_t)N * N;
-  cplx *x0 = pl.take<cplx>(LN * B);
-  cplx *x1 = pl.take<cplx>(LN * B);
-  cplx *P = pl.take<cplx>((size_t)L * L);
-  cplx *gx = pl.take<cplx>(L);
-  cplx *gy = pl.take<cplx>(L);
-  cplx *pkx = nullptr, *pky = nullptr;  // torus: the factors P_x, P_y of the propagator
-  if (lat.dim == 2) {
-    pkx = pl.take<cplx>((size_t)lat.Lx * lat.Lx);
-    pky = pl.take<cplx>((size_t)lat.Ly * lat.Ly);
-  }
-  cplx *G = pl.take<cplx>(NN * B);
-  cplx *Rinv = pl.take<cplx>(NN * B);
-  cplx *T = pl.take<cplx>((size_t)N * CHOL_NB * B);
-  double *p = pl.take<double>((size_t)L * B);
-  double *gamma = pl.take<double>(B);
-  uint64_t *uid = pl.take<uint64_t>(B);
-  int *occ = pl.take<int>(N);
-  int *region = pl.take<int>(L);
-  int *flag = pl.take<int>(64);
-  int *pm_sites = pl.take<int>((size_t)L * B);
-  int *pm_out = pl.take<int>((size_t)L * B);
-  int *pm_cnt = pl.take<int>(B);
-  double *pm_prob = pl.take<double>((size_t)L * B);
-  cplx *pm_v = pl.take<cplx>((size_t)N * B);
-  cplx *pm_w = pl.take<cplx>((size_t)L * B);
-  double *pm_u = pl.take<double>((size_t)L * B);
-  double *pm_tau = pl.take<double>((size_t)L * B);
-  int *pm_m1 = pl.take<int>((size_t)L * B);
-  int *pm_k1 = pl.take<int>(B);
-  int *pm_code = pl.take<int>((size_t)L * B);
-  cplx *ev = pl.take<cplx>((size_t)2 * N * B);
-  cplx *ew = pl.take<cplx>((size_t)N * B);
-  cplx *ep = pl.take<cplx>((size_t)N * B);
-  double *etau = pl.take<double>((size_t)2 * B);
-  double *ed = pl.take<double>((size_t)N * B);
-  double *ee = pl.take<double>((size_t)N * B);
-  double *elam = pl.take<double>((size_t)N * B);
-  double *eS = pl.take<double>(B);
-  int64_t *step_base = pl.take<int64_t>(B);
-  const int Lyr = lat.dim == 2 ? lat.Ly : 1, jcap = cont_jcap(lat.Lx, Lyr);
-  double *ct_t = pl.take<double>(B);
-  cplx *ct_g = pl.take<cplx>((size_t)(lat.Lx + Lyr) * B);
-  double *ct_jn = pl.take<double>((size_t)jcap * B);
-  int *ct_info = pl.take<int>((size_t)4 * B);
-  double *ct_dinfo = pl.take<double>((size_t)4 * B);
-  cplx *ct_v = pl.take<cplx>((size_t)N * B);
-  cplx *ct_y = pl.take<cplx>((size_t)L * B);
-  cplx *ct_yp = pl.take<cplx>((size_t)L * B);
-  float *pr32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
-  float *pi32 = precision == MFQ_FP32_BULK ? pl.take<float>((size_t)L * L) : nullptr;
-  if (!c) return;
-  c->Pr32 = pr32; c->Pi32 = pi32;
-  c->X[0] = x0; c->X[1] = x1; c->P = P; c->gx = gx; c->gy = gy; c->Pkx = pkx; c->Pky = pky;
-  c->chol = CholWork{G, Rinv, T, flag, reinterpret_cast<double *>(flag + 32)};
-  c->step_dev = reinterpret_cast<int64_t *>(flag + 48);
-  c->step_base = step_base;
-  // the blocked reduction keeps its panels in Rinv (free outside a step; 4 TRD_NB n <= N^2 for
-  // n >= TRD_BLOCKED_MIN)
-  c->eig = EigWork{G, ev, ew, ep, etau, ed, ee, elam, eS, Rinv, (long)NN};
-  c->p = p; c->gamma = gamma; c->uid = uid; c->occ = occ; c->region = region; c->flag = flag;
-  c->pm_sites = pm_sites; c->pm_out = pm_out; c->pm_cnt = pm_cnt; c->pm_prob = pm_prob;
-  c->pm_v = pm_v; c->pm_w = pm_w;
-  c->pmb = PmBlockedWork{pm_sites, pm_out, pm_cnt, pm_prob, pm_u, pm_tau, pm_m1, pm_k1, pm_code,
-                         G, Rinv, T};
-  c->ct = ContWork{ct_t, ct_g, ct_jn, ct_info, ct_dinfo, ct_v, ct_y, ct_yp, jcap};
+WsLayout layout_of(const mfq_lattice &lat, int N, int B, int precision) {
+  return plan_workspace(lat.dim, lat.Lx, lat.dim == 2 ? lat.Ly : 1, N, B, precision == MFQ_FP32_BULK);
 }
 
 // Generating row of the ring propagator exp(-i Ht dt) from the Jacobi-Anger
@@ -263,14 +221,29 @@ mfq_status collect_phase_times(mfq_ctx *c) {
   return MFQ_OK;
 }
 
+// Clears the error flag and the breakdown record (each in its own 256-byte region).
+hipError_t clear_flag(mfq_ctx *c) {
+  hipError_t e = fill_zero(c->flag, 256, c->stream);
+  if (e == hipSuccess) e = fill_zero(c->info, 256, c->stream);
+  return e;
+}
+
 mfq_status check_flag(mfq_ctx *c) {
   int f = 0;
+  BreakdownInfo info{};
   HIPCHK(hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream), "flag read");
+  HIPCHK(hipMemcpyAsync(&info, c->info, sizeof(info), hipMemcpyDeviceToHost, c->stream), "breakdown read");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   if (f) {
-    HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
+    HIPCHK(clear_flag(c), "flag clear");
     HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
-    return fail(c, MFQ_ENUMERIC, "Cholesky breakdown (non-positive or non-finite pivot)");
+    static const char *src[] = {"unknown source", "Cholesky-QR pass 1", "Cholesky-QR pass 2", "fused kernel"};
+    char where[192] = "";
+    if (info.set)
+      std::snprintf(where, sizeof(where), ": %s, trajectory %d, column %d, pivot %.17g",
+                    src[(info.source >= 1 && info.source <= 3) ? info.source : 0], info.traj, info.col,
+                    info.pivot);
+    return fail(c, MFQ_ENUMERIC, std::string("Cholesky breakdown (non-positive or non-finite pivot)") + where);
   }
   return MFQ_OK;
 }
@@ -602,9 +575,7 @@ mfq_status mfq_workspace_bytes(const mfq_lattice *lat, int32_t N, int32_t n_traj
     return MFQ_EINVAL;
   const int L = lattice_L(lat);
   if (N < 1 || N >= L) return MFQ_EINVAL;
-  Plan pl;
-  carve(pl, *lat, L, N, n_traj, precision, nullptr);
-  *bytes = pl.off + 256;
+  *bytes = layout_of(*lat, N, n_traj, precision).total + 256;
   return MFQ_OK;
 }
 
@@ -639,9 +610,8 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
     }
   }
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, MFQ_EDEVICE, "hipSetDevice");
-  Plan sizing;
-  carve(sizing, *lat, L, N, n_traj, precision, nullptr);
-  const size_t need = sizing.off + 256;
+  const WsLayout wl = layout_of(*lat, N, n_traj, precision);
+  const size_t need = wl.total + 256;
   if (c->own_ws && c->ws) {
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(c->ws);
@@ -661,9 +631,7 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
     c->ws_bytes = need;
   }
   drop_graph(c);
-  Plan pl;
-  pl.base = reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws)));
-  carve(pl, *lat, L, N, n_traj, precision, c);
+  carve(reinterpret_cast<char *>(align_up(reinterpret_cast<size_t>(c->ws))), wl, *lat, N, c);
   c->lat = *lat;
   c->L = L; c->N = N; c->B = n_traj; c->precision = precision;
   c->step = 0; c->cur = 0; c->dt_cached = NAN; c->ct_any = false;
@@ -672,7 +640,8 @@ mfq_status mfq_init_state(mfq_ctx *c, const mfq_lattice *lat, int32_t N, int32_t
          "uid upload");
   HIPCHK(hipMemcpyAsync(c->occ, occ.data(), N * sizeof(int), hipMemcpyHostToDevice, c->stream),
          "occupied upload");
-  HIPCHK(fill_zero(c->flag, 256, c->stream), "flag clear");
+  HIPCHK(clear_flag(c), "flag clear");
+  HIPCHK(fill_zero(c->step_dev, 256, c->stream), "step counter clear");
   HIPCHK(fill_zero(c->pm_cnt, ((size_t)n_traj * sizeof(int) + 7) / 8 * 8, c->stream), "event clear");
   HIPCHK(fill_zero(c->step_base, (size_t)n_traj * sizeof(int64_t), c->stream), "step base clear");
   HIPCHK(cont_clock_set(c->ct.t, 0, n_traj, 0.0, c->stream), "clock clear");
@@ -935,6 +904,7 @@ mfq_status mfq_run_group(mfq_ctx *const *ctxs, mfq_run_args *args, int32_t n) {
     a.max_obs = r.n_obs; a.S_out = c->run_S;
     a.ev_sites = c->pm_sites; a.ev_out = c->pm_out; a.ev_cnt = c->pm_cnt; a.ev_prob = c->pm_prob;
     a.flag = c->flag;
+    a.info = c->info;
     a.B = c->B;
     grp.first[k + 1] = grp.first[k] + c->B;
   }
@@ -1073,6 +1043,7 @@ mfq_status mfq_run(mfq_ctx *c, int32_t protocol, const double *gamma, double dt,
   a.max_obs = n_obs; a.S_out = c->run_S;
   a.ev_sites = c->pm_sites; a.ev_out = c->pm_out; a.ev_cnt = c->pm_cnt; a.ev_prob = c->pm_prob;
   a.flag = c->flag;
+  a.info = c->info;
   a.B = c->B;
   {
     PhaseTimer t(c, MFQ_PHASE_PROPAGATE);

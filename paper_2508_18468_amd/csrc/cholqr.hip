@@ -13,108 +13,68 @@
 // result in place when its Gram certifies |U^+ U - I| <= CHOL_KEEP_MAX entrywise,
 // so that, as in every step of the workloads here, it costs one Gram and no copy.
 #include "mfq_internal.h"
+#include "potrf_block.h"
 
 namespace mfq {
 
 namespace {
 
 constexpr int NB = CHOL_NB;
+static_assert(PB == NB, "one diagonal block size");
 
 // Factorise the w x w diagonal block at (c0, c0) of G[b] (upper triangle),
 // write R_JJ back into G and R_JJ^{-1} (full block, zeros below the diagonal)
-// into Rinv[b].  A non-positive or non-finite pivot raises *flag.
-//
-// The elimination runs without square roots: step k subtracts
-// conj(G_ki) G_kj / G_kk from the trailing upper triangle, one barrier per
-// step, each thread owning a fixed 4 x 4 set of (row, column) positions; the
-// rows of R are scaled by 1/sqrt(G_kk) afterwards.  The inverse is formed by
-// back substitution with four lanes per column and kept transposed in the free
-// lower triangle of the same LDS array (its diagonal apart), so that two
-// workgroups fit on a compute unit.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(cplx *G, cplx *Rinv, int N, int c0, int w,
-                                                         int *flag, const double *skip_if_le,
-                                                         double skip_thr) {
+// into Rinv[b], by the phases of potrf_block.h separated by barriers.  A
+// non-positive or non-finite pivot raises *flag, and the first such pivot of a
+// call sequence is recorded in *info (source: 1 or 2 for the pass, the
+// trajectory, its column and its value).  The block and its inverse share one
+// LDS array, so that two workgroups fit on a compute unit.
+__global__ __launch_bounds__(PB_THREADS) void potrf_diag_kernel(cplx *G, cplx *Rinv, int N, int c0, int w,
+                                                                int *flag, BreakdownInfo *info, int source,
+                                                                const double *skip_if_le, double skip_thr) {
   if (skip_if_le && *skip_if_le <= skip_thr) return;
   const int b = blockIdx.x, tid = threadIdx.x;
   cplx *Gb = G + (long)b * N * N;
   cplx *Rb = Rinv + (long)b * N * N;
-  // a[c][r], r <= c: element (row r, col c) of the block, then of R; a[r][c], r < c: element
-  // (r, c) of R^{-1}; xd: the diagonal of R^{-1}
-  __shared__ cplx a[NB][NB + 1];
-  __shared__ double xd[NB];
-  __shared__ double rs[NB];       // sqrt of the pivots
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
-  for (int c = tid >> 6; c < w; c += 4)
-    for (int r = tid & 63; r < w; r += 64)
-      a[c][r] = (r <= c) ? Gb[(c0 + r) + (long)(c0 + c) * N] : cplx{0.0, 0.0};
+  __shared__ PotrfLds s;
+  __shared__ int first_bad;  // smallest column of a bad pivot (w: none)
+  if (tid == 0) first_bad = w;
+  potrf_load(s, Gb, N, c0, w, tid);
   __syncthreads();
-  const int ti = tid & 15, tj = tid >> 4;  // rows ti + 16 p, columns tj + 16 q
   for (int k = 0; k + 1 < w; ++k) {
-    double d = a[k][k].re;
-    if (!(d > 0.0) || !isfinite(d)) d = 1.0;  // flagged below
-    const double inv = 1.0 / d;
-#pragma unroll
-    for (int q = 0; q < NB / 16; ++q) {
-      const int j = tj + 16 * q;
-      if (j <= k || j >= w) continue;
-      const cplx gkj = a[j][k];
-      const double fr = gkj.re * inv, fi = gkj.im * inv;
-#pragma unroll
-      for (int p = 0; p < NB / 16; ++p) {
-        const int i = ti + 16 * p;
-        if (i <= k || i > j) continue;
-        const cplx gki = a[i][k];  // a[j][i] -= conj(G_ki) G_kj / G_kk
-        a[j][i].re -= gki.re * fr + gki.im * fi;
-        a[j][i].im -= gki.re * fi - gki.im * fr;
-      }
-    }
+    potrf_eliminate(s, k, w, tid);
     __syncthreads();
   }
-  if (tid < w) {
-    const double d = a[tid][tid].re;
-    if (!(d > 0.0) || !isfinite(d)) {
-      bad = 1;
-      rs[tid] = 1.0;
-    } else {
-      rs[tid] = sqrt(d);
-    }
-  }
+  if (tid < w && potrf_pivot(s, tid)) atomicMin(&first_bad, tid);
   __syncthreads();
-  for (int c = tid >> 6; c < w; c += 4)
-    for (int r = tid & 63; r <= c; r += 64) {
-      const double sc = 1.0 / rs[r];
-      a[c][r] = r == c ? cplx{rs[r], 0.0} : cplx{a[c][r].re * sc, a[c][r].im * sc};
-    }
+  potrf_scale(s, w, tid);
   __syncthreads();
-  // inverse of the upper triangular block: column j by lanes 4j .. 4j+3; element (l, j) of the
-  // inverse (l < j) lives at a[l][j]
+  // column j of the inverse by lanes 4j .. 4j+3 of one wave
   const int j = tid >> 2, q = tid & 3;
   if (j < w) {
-    const double dj = 1.0 / a[j][j].re;
-    if (q == 0) xd[j] = dj;
+    const double dj = 1.0 / s.a[j][j].re;
+    if (q == 0) s.xd[j] = dj;
     for (int i = j - 1; i >= 0; --i) {
-      double sr = 0.0, si = 0.0;
-      for (int l = i + 1 + q; l <= j; l += 4) {
-        const cplx r = a[l][i], t = l == j ? cplx{dj, 0.0} : a[l][j];
-        sr += r.re * t.re - r.im * t.im;
-        si += r.re * t.im + r.im * t.re;
-      }
+      double sr, si;
+      potrf_inv_partial(s, i, j, q, dj, sr, si);
       sr += __shfl_xor(sr, 1, 64);
       si += __shfl_xor(si, 1, 64);
       sr += __shfl_xor(sr, 2, 64);
       si += __shfl_xor(si, 2, 64);
-      const double inv = 1.0 / a[i][i].re;
-      a[i][j] = cplx{-sr * inv, -si * inv};  // the four lanes store the same value
+      potrf_inv_store(s, i, j, sr, si);  // the four lanes store the same value
     }
   }
   __syncthreads();
-  for (int c = tid >> 6; c < w; c += 4)
-    for (int r = tid & 63; r < w; r += 64) {
-      if (r <= c) Gb[(c0 + r) + (long)(c0 + c) * N] = a[c][r];
-      Rb[(c0 + r) + (long)(c0 + c) * N] = r < c ? a[r][c] : (r == c ? cplx{xd[r], 0.0} : cplx{0.0, 0.0});
+  potrf_store(s, Gb, Rb, N, c0, w, tid);
+  if (tid == 0 && first_bad < w) {
+    atomicOr(flag, 1);
+    if (atomicCAS(&info->set, 0, 1) == 0) {
+      info->source = source;
+      info->traj = b;
+      info->col = c0 + first_bad;
+      info->pivot = s.piv[first_bad];
     }
-  if (tid == 0 && bad) atomicOr(flag, 1);
+  }
 }
 
 // Pass 2 did not certify its input (max |G - I| above thr or not finite): its product,
@@ -168,7 +128,7 @@ hipError_t cholqr_pass(cplx *Uin, cplx *Uout, int L, int N, int B, const CholWor
     for (int c0 = p0; c0 < p1; c0 += NB) {
       const int w = std::min(NB, p1 - c0);
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(B), dim3(256), 0, s, wk.G, wk.Rinv, N, c0, w, wk.flag,
-                         skip, thr);
+                         wk.info, near_identity ? 2 : 1, skip, thr);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const int r0 = c0 + w, nr = N - r0;
       if (nr <= 0) break;

@@ -792,11 +792,6 @@ __global__ void clock_set_kernel(double *t, int first, int count, double value) 
 
 }  // namespace
 
-int cont_jcap(int Lx, int Ly) {
-  const int Lm = Lx > Ly ? Lx : Ly;
-  return Lm / 2 + (int)std::ceil(std::sqrt(80.0 * Lm + 160.0)) + 64;
-}
-
 hipError_t cont_clock_set(double *t, int first, int count, double value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(clock_set_kernel, dim3((count + 255) / 256), dim3(256), 0, s, t, first, count, value);

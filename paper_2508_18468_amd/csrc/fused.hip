@@ -57,8 +57,10 @@ __host__ __device__ inline FusedLayout fused_layout(int L, int N, int Lx, int Ly
 // R).  X has leading dimension lu (>= L); G (the Gram, then R) has leading
 // dimension lg (>= N); rdiag receives the diagonal of R.  Gram with four
 // independent partial sums per entry, right-looking Cholesky in one wave, then
-// the triangular solve Y R = X (Y overwrites X) one row per thread.
-__device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu, int lg, int *bad) {
+// the triangular solve Y R = X (Y overwrites X) one row per thread.  A non-positive or
+// non-finite pivot sets *bad to its column + 1 and *bad_pivot to its value (first one only).
+__device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu, int lg, int *bad,
+                           double *bad_pivot) {
   const int tid = threadIdx.x;
   for (int idx = tid; idx < N * N; idx += 256) {
     const int a = idx % N, c = idx / N;
@@ -89,12 +91,13 @@ __device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu
     for (int k = 0; k < N; ++k) {
       double d = G[k + k * lg].re;
       const bool ok = d > 0.0 && isfinite(d);
+      if (lane == 0 && !ok && *bad == 0) {
+        *bad = k + 1;
+        *bad_pivot = d;
+      }
       if (!ok) d = 1.0;
       const double rkk = sqrt(d);
-      if (lane == 0) {
-        rdiag[k] = rkk;
-        if (!ok) *bad = 1;
-      }
+      if (lane == 0) rdiag[k] = rkk;
       for (int j = k + 1 + lane; j < N; j += 64) {
         G[k + j * lg].re /= rkk;
         G[k + j * lg].im /= rkk;
@@ -156,6 +159,7 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
   cplx *gy = reinterpret_cast<cplx *>(smem + f.gy);
   __shared__ double red[4];
   __shared__ int bad;
+  __shared__ double bad_pivot;
 
   const int tid = threadIdx.x;
   const int L = a.L, N = a.N, lu = L + 1, lg = N + 1;
@@ -231,8 +235,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
                                   lu);
       __syncthreads();
     }
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad);
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad);
+    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot);
+    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot);
     // state now in Ub: swap so that it is in Ua for the next step
     cplx *t = Ua;
     Ua = Ub;
@@ -290,7 +294,15 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
     }
     if (tid == 0) a.ev_cnt[b] = last_cnt;
   }
-  if (tid == 0 && bad) atomicOr(a.flag, 1);
+  if (tid == 0 && bad) {
+    atomicOr(a.flag, 1);
+    if (atomicCAS(&a.info->set, 0, 1) == 0) {
+      a.info->source = 3;
+      a.info->traj = b;
+      a.info->col = bad - 1;
+      a.info->pivot = bad_pivot;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void fused_trajectory_kernel(FusedArgs a) {

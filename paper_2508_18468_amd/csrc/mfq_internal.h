@@ -5,11 +5,10 @@
 #include <cstdint>
 #include <cstddef>
 
-namespace mfq {
+#include "cplx.h"
+#include "workspace_layout.h"
 
-struct cplx {
-  double re, im;
-};
+namespace mfq {
 
 // ---------------------------------------------------------------- batched complex GEMM
 // D[b] = alpha * op(A[b]) * op(B[b]) + beta * Cin[b], column-major, complex FP64.
@@ -130,8 +129,6 @@ struct ContWork {
   cplx *yp;       // B x L: P(tau) y
   int jcap;
 };
-// Scratch length per trajectory for the Bessel recurrence of rings up to max(Lx, Ly).
-int cont_jcap(int Lx, int Ly);
 hipError_t cont_clock_set(double *t, int first, int count, double value, hipStream_t s);
 // One event on every trajectory whose clock is below t_end.  Ua holds the state;
 // the result lands in Ub on the ring (*state_in_b = true) and back in Ua on the
@@ -175,14 +172,13 @@ hipError_t rk4_homodyne(cplx *U, cplx *V1, cplx *V2, const double *p, double *a,
 
 // ---------------------------------------------------------------- Cholesky-QR
 struct CholWork {
-  cplx *G;       // N x N per trajectory (upper triangle used)
-  cplx *Rinv;    // N x N per trajectory
-  cplx *T;       // N x NB per trajectory
-  int *flag;     // device error flag
-  double *dev;   // device scalar: max |G - I| of the latest near-identity check
+  cplx *G;              // N x N per trajectory (upper triangle used)
+  cplx *Rinv;           // N x N per trajectory
+  cplx *T;              // N x NB per trajectory
+  int *flag;            // device error flag
+  BreakdownInfo *info;  // where the first breakdown was seen (set with the flag)
+  double *dev;          // device scalar: max |G - I| of the latest near-identity check
 };
-constexpr int CHOL_NB = 64;
-constexpr int CHOL_OUTER = 8 * CHOL_NB;  // rows of R per outer panel of the blocked Cholesky
 // Largest |U^+ U - I| entry for which the second pass uses the first-order factor.
 constexpr double CHOL_FIRST_ORDER_MAX = 1e-8;
 // Largest |U^+ U - I| entry for which the second pass keeps U as it is: the first pass
@@ -218,6 +214,7 @@ struct FusedArgs {
   int *ev_sites, *ev_out, *ev_cnt;  // projective events of the last step (L per trajectory)
   double *ev_prob;
   int *flag;
+  BreakdownInfo *info;
   int B;                    // trajectories of this context (row length of S_out)
 };
 bool fused_fits(int L, int N, int Lx, int Ly);
@@ -244,18 +241,11 @@ struct EigWork {
   cplx *panel;        // blocked reduction: panel factors and partial sums (trd_panel_elems(n))
   long panel_stride;  // between trajectories
 };
-// Panel width of the blocked Householder reduction, which takes batches of n >= TRD_BLOCKED_MIN
-// with B n^2 >= TRD_BLOCKED_WORK (below that the per-reflector sweep, with fewer launches per
-// column, is faster: launch latency rather than HBM traffic bounds the reduction there).
-constexpr int TRD_NB = 32;
-constexpr int TRD_BLOCKED_MIN = 512;
+// The blocked Householder reduction (panel width TRD_NB, storage trd_panel_elems) takes
+// batches of n >= TRD_BLOCKED_MIN with B n^2 >= TRD_BLOCKED_WORK (below that the per-reflector
+// sweep, with fewer launches per column, is faster: launch latency rather than HBM traffic
+// bounds the reduction there).
 constexpr double TRD_BLOCKED_WORK = 16777216.0;
-// Complex entries of the blocked reduction's per-matrix storage: X and Y (n x 2 TRD_NB each),
-// 16 row chunks of z partial sums (2 TRD_NB each), one v^+ y partial per 32 rows, and the row
-// and column sums of A v per 64 x 64 tile (two n-vectors per tile row or column).
-inline long trd_panel_elems(int n) {
-  return (long)4 * TRD_NB * n + 16L * 2 * TRD_NB + (n + 31) / 32 + 2L * ((n + 63) / 64) * n;
-}
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,
                        int *n_out, hipStream_t s);
 hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s);

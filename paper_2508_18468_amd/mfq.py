@@ -270,11 +270,14 @@ def mfq_set_times(ctx, t):
     _check(ctx, lib().mfq_set_times(ctx, _ptr(tt)))
 
 
-def mfq_get_state(ctx, n_traj, L, N):
-    U = np.zeros((n_traj, N, L), dtype=np.complex128)  # column-major L x N per trajectory
+def mfq_get_state(ctx, n_traj, L, N, contiguous=True):
+    """(U, step); U[b] is L x N.  contiguous=False returns the transposed view of the
+    column-major download (no second copy: large states)."""
+    U = np.empty((n_traj, N, L), dtype=np.complex128)  # column-major L x N per trajectory
     step = ctypes.c_int64()
     _check(ctx, lib().mfq_get_state(ctx, _ptr(U), ctypes.byref(step)))
-    return np.ascontiguousarray(U.transpose(0, 2, 1)), step.value
+    V = U.transpose(0, 2, 1)
+    return (np.ascontiguousarray(V) if contiguous else V), step.value
 
 
 def mfq_set_state(ctx, U, step):
@@ -524,8 +527,8 @@ class Trajectories:
     def set_times(self, t):
         mfq_set_times(self.ctx, np.broadcast_to(np.asarray(t, dtype=np.float64), (self.n_traj,)))
 
-    def get_state(self):
-        return mfq_get_state(self.ctx, self.n_traj, self.L, self.N)
+    def get_state(self, contiguous=True):
+        return mfq_get_state(self.ctx, self.n_traj, self.L, self.N, contiguous)
 
     def set_state(self, U, step):
         mfq_set_state(self.ctx, U, step)

@@ -80,3 +80,38 @@ def test_engine_rejects_job_larger_than_budget():
     with pytest.raises(mfq.MfqError):
         eng.submit(1, 63, 1, QSD, 0.5, 0.05, 10, 0, 2, [0])  # odd L: no Neel state
     eng.close()
+
+
+def test_served_jobs_at_mix_sizes_match_oracle():
+    """Jobs of the served mix's own shapes (1d L = 256 and 512, 2d 16 x 16; both protocols, rates
+    drawn in [0.1, 2.0]) submitted together with smaller filler jobs, so that they share the
+    device with other groups; each job's final entropy against the CPU oracle run of the same
+    job (seed, uid, rate), |dS| <= 1e-9."""
+    import oracle
+    from paper_2508_18468_amd import mfq
+    rng = np.random.default_rng(11)
+    shapes = [(1, 256, 1), (1, 512, 1), (2, 16, 16)]
+    jobs = []
+    for i, (dim, Lx, Ly) in enumerate(shapes * 2):
+        L = Lx * Ly
+        region = list(range(L // 2)) if dim == 1 else sorted(x + Lx * y for y in range(Ly) for x in range(Lx // 2))
+        jobs.append(dict(dim=dim, Lx=Lx, Ly=Ly, protocol=PM if i < 3 else QSD,
+                         gamma=float(rng.uniform(0.1, 2.0)), n_steps=int(rng.choice([24, 30])), uid=7000 + i,
+                         region=region))
+    fillers = [dict(dim=1, Lx=64, Ly=1, protocol=QSD, gamma=0.7, n_steps=200, uid=7100 + k,
+                    region=list(range(32))) for k in range(4)]
+    eng = mfq.Engine(max_slots=4)
+    ids = []
+    for j in fillers + jobs:
+        ids.append(eng.submit(j["dim"], j["Lx"], j["Ly"], j["protocol"], j["gamma"], 0.05, j["n_steps"], 0,
+                              j["uid"], j["region"]))
+    res = [eng.wait(i, 300) for i in ids]
+    eng.close()
+    for j, (S, _) in zip(jobs, res[len(fillers):]):
+        lat = oracle.Lattice(j["dim"], j["Lx"], j["Ly"])
+        P = oracle.propagator(lat, 0.05)
+        out = oracle.run_trajectory(P, oracle.default_occupied(lat), j["protocol"], j["gamma"], 0.05, 0,
+                                    j["uid"], j["n_steps"])
+        ref = oracle.entanglement_entropy(out["U"], j["region"])
+        assert S.shape == (1,)
+        assert abs(S[0] - ref) <= 1e-9, (j, S[0], ref)

@@ -56,3 +56,27 @@ def test_fp32_bulk_projective_short_run():
     ref = ob.entropy(list(range(32)))
     assert np.abs(S - ref).max() <= 1e-4 * max(ref.max(), 1.0)
     sim.close()
+
+
+def test_fp32_bulk_ring1024_against_fp64_oracle():
+    """The benchmark ring (L = 1024, N = 512, homodyne, dt = 0.05) in the FP32-bulk form: three
+    trajectories of the batch (uids 5, 205, 383: one per rate 0.1, 0.3, 1.0) over 100 steps
+    (the first observation of the workload) against the FP64 oracle, |dS|/S <= 1e-4."""
+    from paper_2508_18468_amd.workloads import ring_qsd_batched
+    w = ring_qsd_batched()
+    uids = [5, 128 + 77, 256 + 127]
+    gam = [w.gammas[u // w.n_traj] for u in uids]
+    sim = _fp32_sim(w.Lx, len(uids), uids)
+    ob = OracleBatch(1, w.Lx, 1, w.dt, uids)
+    sim.step(QSD, gam, w.dt, w.seed, 100)
+    for _ in range(100):
+        ob.step(QSD, gam, w.seed)
+    S = sim.entropy(w.regions[0])
+    ref = ob.entropy(w.regions[0])
+    rel = np.abs(S - ref) / ref
+    print("fp32-bulk ring1024 |dS|/S after 100 steps:", rel)
+    assert rel.max() <= 1e-4
+    U, _ = sim.get_state()
+    for t in range(len(uids)):
+        assert np.abs(np.conj(U[t].T) @ U[t] - np.eye(w.N)).max() < 1e-12
+    sim.close()

@@ -5,6 +5,8 @@ invariants (U^+ U = 1, C^2 = C, Tr C = N) to 1e-10, Born probabilities to 1e-12,
 projective outcomes identical (integer decisions taken in FP64 on both sides).
 """
 
+import re
+
 import numpy as np
 import pytest
 
@@ -202,9 +204,31 @@ def test_errors_are_reported():
     sim.close()
 
 
+def test_cholesky_breakdown_is_located():
+    """A state with an exactly zero column (trajectory 1, column 5) gives an exactly zero pivot
+    in the first Cholesky-QR pass (gamma = 0 keeps the column zero through the propagator and
+    the homodyne factor); the error names the pass, trajectory, column and pivot, and the flag
+    is cleared after it is reported."""
+    from paper_2508_18468_amd import mfq
+    sim = make_sim(1, 32, n_traj=3)
+    U, st = sim.get_state()
+    U[1, :, 5] = 0.0
+    sim.set_state(U, st)
+    sim.step(QSD, [0.0, 0.0, 0.0], 0.05, 0, 1)
+    with pytest.raises(mfq.MfqError) as e:
+        sim.get_state()
+    assert e.value.code == -4
+    msg = str(e.value)
+    assert re.search(r"pass 1, trajectory 1, column 5, pivot -?0$", msg), msg
+    sim.get_state()  # cleared
+    sim.close()
+
+
 def test_batched_homodyne_ring_full_size_sampled():
     """1d ring L=1024, N=512, homodyne gamma in {0.1, 0.3, 1.0} x 128 trajectories in one batch
-    (the benchmark's launch configuration); three sampled trajectories checked against the oracle."""
+    (the benchmark's launch configuration: steps in captured step-pair graphs), the first 20
+    steps; three sampled trajectories (one per rate) checked against the oracle: |dS| <= 1e-9
+    after steps 1, 2, 5, 10, 15 and 20, C to 1e-10 after step 20, Born probabilities to 1e-12."""
     from paper_2508_18468_amd.workloads import ring_qsd_batched
     w = ring_qsd_batched()
     uids = w.uids(0) + w.uids(1) + w.uids(2)
@@ -212,16 +236,21 @@ def test_batched_homodyne_ring_full_size_sampled():
     sim = make_sim(1, w.Lx, n_traj=len(uids), uids=uids)
     sample = [5, 128 + 77, 256 + 127]
     ob = OracleBatch(1, w.Lx, 1, w.dt, uids)
-    for n in range(2):
-        sim.step(QSD, gam, w.dt, w.seed)
-        ob.step(QSD, gam, w.seed, idx=sample)
-    S = sim.entropy(w.regions[0])
-    ref = ob.entropy(w.regions[0], idx=sample)
-    for t in sample:
-        assert abs(S[t] - ref[t]) <= 1e-9
+    done = 0
+    for target in (1, 2, 5, 10, 15, 20):
+        sim.step(QSD, gam, w.dt, w.seed, target - done)
+        for _ in range(target - done):
+            ob.step(QSD, gam, w.seed, idx=sample)
+        done = target
+        S = sim.entropy(w.regions[0])
+        ref = ob.entropy(w.regions[0], idx=sample)
+        for t in sample:
+            assert abs(S[t] - ref[t]) <= 1e-9, (target, t, S[t], ref[t])
     U, _ = sim.get_state()
+    p = sim.occupations()
     for t in sample:
         assert np.abs(corr(U[t]) - corr(ob.U[t])).max() < 1e-10
+        assert np.abs(p[t] - oracle.born_probabilities(ob.U[t])).max() <= 1e-12
     sim.close()
 
 

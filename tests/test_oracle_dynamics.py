@@ -35,6 +35,36 @@ def neel_free_closed_form(lat, t):
     return C + 0.5 * s[:, None] * acc / L
 
 
+def neel_free_entries(lat, t, a, b):
+    """Entries C_ab(t) of neel_free_closed_form for site lists a, b, at any lattice size: the
+    sum over k factorises, (1/L) sum_k e^{ik(r_a - r_b)} e^{2 i eps_k t} = f_x(dx) f_y(dy) with
+    f(d) = (1/Lr) sum_m e^{i k_m d} e^{4 i J t cos k_m} on a ring of Lr sites (f_y = 1 in 1d)."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+
+    def ring_table(Lr):
+        m = np.arange(Lr)
+        k = 2 * np.pi * m / Lr
+        md = np.outer(np.arange(Lr), m) % Lr  # m d reduced first: accurate phases
+        return (np.exp(2j * np.pi * md / Lr) * np.exp(4j * lat.J * t * np.cos(k))[None, :]).sum(axis=1) / Lr
+
+    xa, ya, xb, yb = a % lat.Lx, a // lat.Lx, b % lat.Lx, b // lat.Lx
+    val = ring_table(lat.Lx)[(xa - xb) % lat.Lx]
+    if lat.dim == 2:
+        val = val * ring_table(lat.Ly)[(ya - yb) % lat.Ly]
+    s = (-1.0) ** (xa + ya)
+    return 0.5 * (a == b) + 0.5 * s * val
+
+
+@pytest.mark.parametrize("lat", [Lattice(1, 64), Lattice(2, 8, 6), Lattice(2, 10, 4)])
+def test_free_entries_equal_full_closed_form(lat):
+    t = 1.3
+    C = neel_free_closed_form(lat, t)
+    a, b = np.meshgrid(np.arange(lat.L), np.arange(lat.L), indexing="ij")
+    E = neel_free_entries(lat, t, a.ravel(), b.ravel()).reshape(lat.L, lat.L)
+    assert np.abs(E - C).max() < 1e-13
+
+
 @pytest.mark.parametrize("lat", [Lattice(1, 64), Lattice(2, 8, 6)])
 @pytest.mark.parametrize("protocol", [PROJECTIVE, HOMODYNE])
 def test_free_evolution_closed_form(lat, protocol):
