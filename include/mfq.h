@@ -77,6 +77,8 @@ typedef struct {
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
  * order all work on, or NULL (the library then creates and owns a stream).
+ * The first context on a device also resolves that device's address of the static
+ * buffer of mfq_density_correlation_noalloc.
  * *out receives the context.  Errors: MFQ_EINVAL, MFQ_EDEVICE. */
 mfq_status mfq_create(int device, void *hip_stream, mfq_ctx **out);
 
@@ -148,6 +150,24 @@ mfq_status mfq_mutual_info(mfq_ctx *ctx, const int32_t *A, int32_t nA, const int
  * Allocates a buffer on first use.  Synchronises.
  * Errors: MFQ_EINVAL (not a 1d lattice, NULL output), MFQ_ESTATE, MFQ_ENOMEM, MFQ_EDEVICE. */
 mfq_status mfq_density_correlation(mfq_ctx *ctx, double *Cr_host);
+
+/* Bytes of the per-GPU static buffer of mfq_density_correlation_noalloc (64 MiB). */
+#define MFQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* mfq_density_correlation for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that forbid it): the
+ * same kernels and the same result, bitwise, but the tile partials and the L/2 bins of every
+ * trajectory go to a static device buffer of MFQ_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends, resolved once per device by mfq_create.
+ * Nothing is allocated or freed on the device by this call.
+ * Limit: (tile partials + L/2) x n_traj doubles must fit the buffer (for example L = 1024 with
+ * up to 384 trajectories); larger requests fail with MFQ_ENOMEM before any launch.
+ * The buffer is shared by every call on that GPU: calls that overlap on one GPU (contexts on
+ * different streams or threads running this call at the same time) race and give wrong
+ * results; sequential calls are safe (the call synchronises its stream before it returns,
+ * and every value it reads from the buffer is written earlier in the same call).
+ * Errors: as mfq_density_correlation, plus MFQ_ENOMEM above the limit. */
+mfq_status mfq_density_correlation_noalloc(mfq_ctx *ctx, double *Cr_host);
 
 /* Particle-number covariance of Sec. IV, Eq. (5): G_AB = -sum_{i in A, j in B} C_ij
  * = sum_{i in A, j in B} |C_ij|^2 for disjoint site lists A and B (ascending), i.e. minus

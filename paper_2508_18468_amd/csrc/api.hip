@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,35 @@
 #include "mfq_internal.h"
 
 using namespace mfq;
+
+// Static device buffer of mfq_density_correlation_noalloc.  Each GPU holds its own copy for
+// the lifetime of the process; host code may use only the per-device address resolved by
+// hipGetSymbolAddress (the name itself is a host-side stand-in, not a device address).
+static __device__ __align__(256) double scratch[MFQ_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_dev;  // per device; null until resolved
+
+// Resolves `device`'s address of the static buffer once (the device must be current).
+hipError_t resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (g_scratch_dev[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[device] = static_cast<double *>(ptr);
+  return hipSuccess;
+}
+
+double *scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device < (int)g_scratch_dev.size() ? g_scratch_dev[device] : nullptr;
+}
+
+}  // namespace
 
 struct mfq_ctx {
   int device = 0;
@@ -531,7 +561,7 @@ mfq_status mfq_create(int device, void *hip_stream, mfq_ctx **out) {
   mfq_ctx *c = new (std::nothrow) mfq_ctx();
   if (!c) return MFQ_ENOMEM;
   c->device = device;
-  if (hipSetDevice(device) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || resolve_scratch(device) != hipSuccess) {
     delete c;
     return MFQ_EDEVICE;
   }
@@ -1072,7 +1102,11 @@ mfq_status ensure_red(mfq_ctx *c, size_t n) {
 
 }  // namespace
 
-mfq_status mfq_density_correlation(mfq_ctx *c, double *Cr_host) {
+namespace {
+
+// C(r) of every trajectory with its tile partials and bins in `buf` (cap doubles; null: the
+// context's buffer, grown on demand).
+mfq_status density_correlation(mfq_ctx *c, double *Cr_host, double *buf, size_t cap) {
   if (!c) return MFQ_EINVAL;
   if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
   if (!Cr_host) return fail(c, MFQ_EINVAL, "Cr_host is NULL");
@@ -1087,17 +1121,38 @@ mfq_status mfq_density_correlation(mfq_ctx *c, double *Cr_host) {
   g.B = c->X[c->cur]; g.ldb = L; g.sB = (long)L * c->N; g.opB = OP_C;
   g.tri = TRI_UPPER;
   const size_t np = zgemm_partials(g), nout = (size_t)half * c->B;
-  mfq_status st = ensure_red(c, np + nout);
-  if (st) return st;
-  g.part = c->red_buf;
+  if (buf) {
+    if (np + nout > cap)
+      return fail(c, MFQ_ENOMEM, "C(r) needs " + std::to_string((np + nout) * sizeof(double)) +
+                                     " bytes of partials and bins, above the static buffer's " +
+                                     std::to_string(cap * sizeof(double)));
+  } else {
+    mfq_status st = ensure_red(c, np + nout);
+    if (st) return st;
+    buf = c->red_buf;
+  }
+  g.part = buf;
   {
     PhaseTimer t(c, MFQ_PHASE_OBSERVE);
-    HIPCHK(zgemm_ring_bins(g, L, c->red_buf + np, c->stream), "density correlation");
+    HIPCHK(zgemm_ring_bins(g, L, buf + np, c->stream), "density correlation");
   }
-  HIPCHK(hipMemcpyAsync(Cr_host, c->red_buf + np, nout * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+  HIPCHK(hipMemcpyAsync(Cr_host, buf + np, nout * sizeof(double), hipMemcpyDeviceToHost, c->stream),
          "C(r) download");
   HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
   return check_flag(c);
+}
+
+}  // namespace
+
+mfq_status mfq_density_correlation(mfq_ctx *c, double *Cr_host) {
+  return density_correlation(c, Cr_host, nullptr, 0);
+}
+
+mfq_status mfq_density_correlation_noalloc(mfq_ctx *c, double *Cr_host) {
+  if (!c) return MFQ_EINVAL;
+  double *buf = scratch_of(c->device);
+  if (!buf) return fail(c, MFQ_EDEVICE, "static buffer of this device not resolved");
+  return density_correlation(c, Cr_host, buf, MFQ_NOALLOC_SCRATCH_BYTES / sizeof(double));
 }
 
 mfq_status mfq_particle_covariance(mfq_ctx *c, const int32_t *A, int32_t nA, const int32_t *B, int32_t nB,

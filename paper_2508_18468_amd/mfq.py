@@ -103,6 +103,7 @@ _SIGS = {
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_density_correlation_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_propagator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_set_integrator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_run_group": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(RunArgs), ctypes.c_int32]),
@@ -219,6 +220,13 @@ def mfq_density_correlation(ctx, n_traj, L):
     """C(r) of Eq. (2), r = 1 .. L/2, per trajectory: an (n_traj, L//2) array."""
     Cr = np.zeros((n_traj, L // 2))
     _check(ctx, lib().mfq_density_correlation(ctx, _ptr(Cr)))
+    return Cr
+
+
+def mfq_density_correlation_noalloc(ctx, n_traj, L):
+    """As mfq_density_correlation, with the library's per-GPU static buffer (no allocation)."""
+    Cr = np.zeros((n_traj, L // 2))
+    _check(ctx, lib().mfq_density_correlation_noalloc(ctx, _ptr(Cr)))
     return Cr
 
 
@@ -501,6 +509,9 @@ class Trajectories:
 
     def density_correlation(self):
         return mfq_density_correlation(self.ctx, self.n_traj, self.L)
+
+    def density_correlation_noalloc(self):
+        return mfq_density_correlation_noalloc(self.ctx, self.n_traj, self.L)
 
     def particle_covariance(self, A, B):
         return mfq_particle_covariance(self.ctx, A, B, self.n_traj)
