@@ -344,6 +344,26 @@ mfq_status mfq_propagator_band(mfq_ctx *ctx, int32_t *band);
 #define MFQ_PM_BLOCKED 2
 mfq_status mfq_set_pm_path(mfq_ctx *ctx, int32_t path);
 
+/* Form of the Householder reduction to tridiagonal form inside the entropy, spectrum and
+ * mutual-information calls (the eigenvalues of C_A, Sec. II entropy formula).  Same
+ * eigenvalues to rounding either way:
+ *   MFQ_EIG_ONE_STAGE  one reflector at a time on the dense Gram (in LDS for small orders,
+ *                      otherwise grid-wide sweeps or panels of 32 reflectors that read the
+ *                      trailing matrix once per reflector);
+ *   MFQ_EIG_TWO_STAGE  dense -> band of half-width 32 by block reflectors whose two-sided
+ *                      updates are matrix-core products, then band -> tridiagonal by bulge
+ *                      chasing in a persistent kernel whose workgroups wait on each other
+ *                      through progress words (a wait beyond 10 s makes the call return
+ *                      MFQ_EDEVICE); used for orders >= 66 where the Rinv region holds its
+ *                      storage (n^2 / 8 + 160 n complex entries per trajectory, at least about
+ *                      20000), else one stage;
+ *   MFQ_EIG_AUTO       two stages from order 6144 on, one below (default; measured on the
+ *                      MI355X, two stages are faster from about that order). */
+#define MFQ_EIG_AUTO 0
+#define MFQ_EIG_ONE_STAGE 1
+#define MFQ_EIG_TWO_STAGE 2
+mfq_status mfq_set_eig_path(mfq_ctx *ctx, int32_t path);
+
 /* GEMM tile choice of a context (all its contractions, the propagator included). */
 #define MFQ_TILE_AUTO 0   /* 128 x 128 tiles for large contractions, 64 x 64 otherwise */
 #define MFQ_TILE_SMALL 1  /* always 64 x 64 (4 waves) */

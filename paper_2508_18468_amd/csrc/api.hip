@@ -111,6 +111,7 @@ struct mfq_ctx {
   // mfq_run: execution path and its observation buffer; GEMM tile choice
   int run_path = 0;   // MFQ_PATH_AUTO
   int tile_mode = 0;  // MFQ_TILE_AUTO
+  int eig_mode = 0;   // MFQ_EIG_AUTO
   // correlation observables: tile partials and results (allocated on first use)
   double *red_buf = nullptr;
   size_t red_cap = 0;
@@ -167,7 +168,7 @@ void carve(char *base, const WsLayout &w, const mfq_lattice &lat, int N, mfq_ctx
   // for TRD_BLOCKED_MIN <= n <= N)
   c->eig = EigWork{G, (cplx *)at(WS_EV), (cplx *)at(WS_EW), (cplx *)at(WS_EP), (double *)at(WS_ETAU),
                    (double *)at(WS_ED), (double *)at(WS_EE), (double *)at(WS_ELAM), (double *)at(WS_ES),
-                   Rinv, NN};
+                   Rinv, NN, c->flag, c->info};
   c->p = (double *)at(WS_BORN); c->gamma = (double *)at(WS_GAMMA); c->uid = (uint64_t *)at(WS_UID);
   c->occ = (int *)at(WS_OCC); c->region = (int *)at(WS_REGION);
   c->pm_sites = (int *)at(WS_PM_SITES); c->pm_out = (int *)at(WS_PM_OUT); c->pm_cnt = (int *)at(WS_PM_CNT);
@@ -267,6 +268,10 @@ mfq_status check_flag(mfq_ctx *c) {
   if (f) {
     HIPCHK(clear_flag(c), "flag clear");
     HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+    if (info.set && info.source == 4)
+      return fail(c, MFQ_EDEVICE, "tridiagonal reduction: a bulge-chase dependency wait exceeded its limit "
+                                  "(trajectory " + std::to_string(info.traj) + ", sweep " +
+                                  std::to_string(info.col) + ")");
     static const char *src[] = {"unknown source", "Cholesky-QR pass 1", "Cholesky-QR pass 2", "fused kernel"};
     char where[192] = "";
     if (info.set)
@@ -501,11 +506,17 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
   return MFQ_OK;
 }
 
-// The context's GEMM tile choice for the launches of one ABI call.
+// The context's GEMM tile choice and reduction form for the launches of one ABI call.
 struct TileScope {
-  int saved;
-  explicit TileScope(const mfq_ctx *c) : saved(gemm_tile_mode()) { set_gemm_tile_mode(c->tile_mode); }
-  ~TileScope() { set_gemm_tile_mode(saved); }
+  int saved, saved_eig;
+  explicit TileScope(const mfq_ctx *c) : saved(gemm_tile_mode()), saved_eig(eig_path()) {
+    set_gemm_tile_mode(c->tile_mode);
+    set_eig_path(c->eig_mode);
+  }
+  ~TileScope() {
+    set_gemm_tile_mode(saved);
+    set_eig_path(saved_eig);
+  }
 };
 
 void drop_graph(mfq_ctx *c) {
@@ -1004,6 +1015,14 @@ mfq_status mfq_set_pm_path(mfq_ctx *c, int32_t path) {
   if (path != MFQ_PM_AUTO && path != MFQ_PM_WORKGROUP && path != MFQ_PM_BLOCKED)
     return fail(c, MFQ_EINVAL, "unknown projective-measurement path");
   c->pm_path = path;
+  return MFQ_OK;
+}
+
+mfq_status mfq_set_eig_path(mfq_ctx *c, int32_t path) {
+  if (!c) return MFQ_EINVAL;
+  if (path != MFQ_EIG_AUTO && path != MFQ_EIG_ONE_STAGE && path != MFQ_EIG_TWO_STAGE)
+    return fail(c, MFQ_EINVAL, "unknown reduction form");
+  c->eig_mode = path;
   return MFQ_OK;
 }
 

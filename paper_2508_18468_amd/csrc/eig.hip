@@ -784,7 +784,27 @@ hipError_t tridiagonalize_blocked(const EigWork &w, int n, int B, hipStream_t s)
 
 }  // namespace
 
+thread_local int tl_eig_path = EIG_PATH_AUTO;
+void set_eig_path(int mode) { tl_eig_path = mode; }
+int eig_path() { return tl_eig_path; }
+
+namespace {
+
+// Wall-clock ticks of the bulge chase's dependency-wait limit (10 s; a task takes microseconds).
+long long chase_wait_ticks() {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
+                                              hipSuccess || khz <= 0)
+    return 1000000000LL;
+  return 10000LL * khz;
+}
+
+}  // namespace
+
 hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s) {
+  const bool two_ok = n >= 2 * TRD2_SB + 2 && w.panel && w.panel_stride >= trd2_scratch_elems(n) && w.flag && w.info;
+  if (two_ok && (tl_eig_path == EIG_PATH_TWO_STAGE || (tl_eig_path == EIG_PATH_AUTO && n >= TRD2_AUTO_MIN)))
+    return tridiagonalize_two_stage(w, n, B, chase_wait_ticks(), s);
   if (n <= LDS_MAX_N) {
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(B), dim3(256), 0, s, w, n);
     return hipGetLastError();

@@ -238,8 +238,11 @@ struct EigWork {
   cplx *p;      // n per trajectory: A v of the newest reflector
   double *tau;  // 2 per trajectory: tau of the two reflector slots
   double *d, *e, *lam, *S;
-  cplx *panel;        // blocked reduction: panel factors and partial sums (trd_panel_elems(n))
+  cplx *panel;        // blocked reductions: panel factors and partial sums (trd_panel_elems(n),
+                      // trd2_scratch_elems(n))
   long panel_stride;  // between trajectories
+  int *flag;                // the context's error word and breakdown record (a bulge-chase wait
+  BreakdownInfo *info;      // beyond its limit is reported through them)
 };
 // The blocked Householder reduction (panel width TRD_NB, storage trd_panel_elems) takes
 // batches of n >= TRD_BLOCKED_MIN with B n^2 >= TRD_BLOCKED_WORK (below that the per-reflector
@@ -249,6 +252,16 @@ constexpr double TRD_BLOCKED_WORK = 16777216.0;
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,
                        int *n_out, hipStream_t s);
 hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s);
+// Two-stage reduction (eig2.hip) of n x n Grams, n >= 2 TRD2_SB + 2, needing
+// panel_stride >= trd2_scratch_elems(n); wait_ticks bounds each dependency wait of its bulge
+// chase (wall-clock ticks).
+hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wait_ticks, hipStream_t s);
+// Reduction form of tridiagonalize for the calling thread: AUTO (by size), ONE_STAGE, TWO_STAGE
+// (where it applies).  Set by the context around its launches.
+enum { EIG_PATH_AUTO = 0, EIG_PATH_ONE_STAGE = 1, EIG_PATH_TWO_STAGE = 2 };
+constexpr int TRD2_AUTO_MIN = 6144;  // AUTO takes the two-stage form from this order on
+void set_eig_path(int mode);
+int eig_path();
 hipError_t bisect_eigvals(const EigWork &w, int n, int B, hipStream_t s);
 hipError_t entropy_sum(const EigWork &w, int n, int B, hipStream_t s);
 

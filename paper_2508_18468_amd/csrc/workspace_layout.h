@@ -12,6 +12,13 @@
 #include <cstddef>
 #include <cstdint>
 
+// Size helpers that device code also calls (the two-stage reduction's scratch layout).
+#if defined(__HIPCC__)
+#define MFQ_LAYOUT_HD __host__ __device__
+#else
+#define MFQ_LAYOUT_HD
+#endif
+
 namespace mfq {
 
 constexpr int CHOL_NB = 64;  // diagonal block of the blocked Cholesky (and width of its T panel)
@@ -27,6 +34,27 @@ inline long trd_panel_elems(int n) {
   return (long)4 * TRD_NB * n + 16L * 2 * TRD_NB + (n + 31) / 32 + 2L * ((n + 63) / 64) * n;
 }
 
+// Two-stage reduction of region Grams (eig2.hip): band half-width of the first stage, panel
+// rows per workgroup of its column launches, K slices of its deep products, and its per-matrix
+// storage in the Rinv region (complex entries): X = [V W] and Y = [W V] (n x 2 TRD2_SB each),
+// V T (n x TRD2_SB), the K-split partials, four TRD2_SB^2 blocks (V^+ V, T, V^+ X, T^+ V^+ X),
+// tau, the column statistics of the column launches (two per workgroup), and n + 64 ints of
+// progress words and counters of the bulge chase.
+constexpr int TRD2_SB = 32;
+constexpr int TRD2_RPW = 128;
+constexpr int TRD2_KS = 16;
+MFQ_LAYOUT_HD inline int trd2_groups(int n) { return (n - TRD2_SB + TRD2_RPW - 1) / TRD2_RPW; }
+// K-split partials: n^2 / 8 + n entries (the m x TRD2_SB product takes at most m / 512 slices)
+// or TRD2_KS slices of a TRD2_SB x TRD2_SB block, whichever is larger.
+MFQ_LAYOUT_HD inline long trd2_kp_elems(int n) {
+  const long a = (long)n * n / 8 + n, b = (long)TRD2_KS * TRD2_SB * TRD2_SB;
+  return a > b ? a : b;
+}
+MFQ_LAYOUT_HD inline long trd2_scratch_elems(int n) {
+  return (long)n * 5 * TRD2_SB + trd2_kp_elems(n) + 4L * TRD2_SB * TRD2_SB + TRD2_SB +
+         (long)trd2_groups(n) * 2 * (2 + 2 * TRD2_SB) + (n + 64 + 3) / 4;
+}
+
 // Bessel-recurrence scratch length per trajectory (continuous-time protocol) for rings up to
 // max(Lx, Ly): half the ring plus the recurrence's start-order margin.
 inline int cont_jcap(int Lx, int Ly) {
@@ -37,7 +65,8 @@ inline int cont_jcap(int Lx, int Ly) {
 // Device record of the first Cholesky breakdown since the flag was last cleared.
 struct BreakdownInfo {
   int32_t set;     // 0 until a breakdown is recorded
-  int32_t source;  // 1: Cholesky-QR pass 1, 2: pass 2, 3: fused small-lattice kernel
+  int32_t source;  // 1: Cholesky-QR pass 1, 2: pass 2, 3: fused small-lattice kernel,
+                   // 4: a dependency wait of the bulge chase exceeded its limit (no pivot)
   int32_t traj;    // trajectory (batch index) of the pivot
   int32_t col;     // column of the pivot in the N x N Gram
   double pivot;    // its value (non-positive or not finite)

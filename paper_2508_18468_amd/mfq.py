@@ -99,6 +99,7 @@ _SIGS = {
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_set_pm_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "mfq_set_eig_path": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
@@ -298,6 +299,7 @@ def mfq_synchronize(ctx):
 
 
 PATH_AUTO, PATH_FUSED, PATH_LAUNCHES = 0, 1, 2
+EIG_AUTO, EIG_ONE_STAGE, EIG_TWO_STAGE = 0, 1, 2
 
 
 def mfq_run(ctx, protocol, gamma, dt, seed, n_steps, obs_every, region, n_traj, step_now):
@@ -566,6 +568,10 @@ class Trajectories:
 
     def set_pm_path(self, path):
         mfq_set_pm_path(self.ctx, path)
+
+    def set_eig_path(self, path):
+        """EIG_AUTO, EIG_ONE_STAGE or EIG_TWO_STAGE (mfq_set_eig_path)."""
+        _check(self.ctx, lib().mfq_set_eig_path(self.ctx, int(path)))
 
     def set_propagator(self, form):
         mfq_set_propagator(self.ctx, form)

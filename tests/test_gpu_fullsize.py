@@ -90,11 +90,14 @@ def check_region(sim, L, N, region, seed):
     assert abs(S - S_exact) <= tol
 
 
-def test_known_spectrum_ring_16384():
+@pytest.mark.parametrize("path", [1, 2])
+def test_known_spectrum_ring_16384(path):
     """1d ring L=16384, N=8192 (the long-chain projective workload): contiguous regions of
-    1024, 4096 and 8192 sites."""
+    1024, 4096 and 8192 sites, with the one-stage (path 1) and the two-stage (path 2)
+    reduction."""
     L, N = 16384, 8192
     sim = make_sim(1, L, n_traj=1)
+    sim.set_eig_path(path)
     for l, seed in ((1024, 11), (4096, 12), (8192, 13)):
         check_region(sim, L, N, list(range(l)), seed)
     sim.close()
@@ -102,7 +105,7 @@ def test_known_spectrum_ring_16384():
 
 def test_known_spectrum_torus_160():
     """2d torus 160 x 160 (L=25600, N=12800): the union A u B of the strips x in [0, 40) and
-    [80, 120), 12800 sites."""
+    [80, 120), 12800 sites (the default form: two stages at this order)."""
     Lx = Ly = 160
     L, N = Lx * Ly, Lx * Ly // 2
     region = sorted(x + Lx * y for y in range(Ly) for x in list(range(0, 40)) + list(range(80, 120)))
@@ -234,6 +237,7 @@ def test_known_spectrum_blocked_tiled_batch():
     lams = [spectrum_mix(l, rng) for _ in range(B)]
     U = np.concatenate([known_state(L, N, region, lam, rng) for lam in lams])
     sim = make_sim(1, L, n_traj=B)
+    sim.set_eig_path(1)  # the one-stage form (the default takes two stages at this order)
     sim.set_state(U, 0)
     got = sim.region_spectrum(region)
     S = sim.entropy(region)

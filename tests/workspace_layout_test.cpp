@@ -74,6 +74,10 @@ static void check(const Shape &sh, bool fp32) {
   for (int n = TRD_BLOCKED_MIN; n <= sh.N; n += std::max(1, sh.N / 97))
     CHECK((unsigned __int128)trd_panel_elems(n) <= NN);
   if (sh.N >= TRD_BLOCKED_MIN) CHECK((unsigned __int128)trd_panel_elems(sh.N) <= NN);
+  // two-stage reduction storage in Rinv for every region order n <= N the default form gives it
+  for (int n = 1024; n <= sh.N; n += std::max(1, sh.N / 97))
+    CHECK((unsigned __int128)trd2_scratch_elems(n) <= NN);
+  if (sh.N >= 1024) CHECK((unsigned __int128)trd2_scratch_elems(sh.N) <= NN);
   // Cholesky level temporaries (at most N^2 / 2 per trajectory) in the other state buffer
   CHECK(NN / 2 <= LN);
   // per-site vectors of the projective and continuous-time steps: L per trajectory
