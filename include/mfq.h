@@ -249,6 +249,16 @@ mfq_status mfq_get_state(mfq_ctx *ctx, void *U_host, int64_t *step);
  * re-orthonormalise on load. */
 mfq_status mfq_set_state(mfq_ctx *ctx, const void *U_host, int64_t step);
 
+/* The rest of a checkpoint of trajectories admitted by mfq_reset_trajectory: per trajectory
+ * its uid (which keys its random numbers) and the context step at which its own step count
+ * restarted (its Philox step counter is the context step minus this base).  Host arrays of
+ * n_traj entries.  mfq_set_slots restores them after mfq_set_state (bases within
+ * [0, the context's step]), so that a resumed context draws exactly what the uninterrupted one
+ * would.  Both synchronise.  Errors: MFQ_EINVAL (NULL, base out of range), MFQ_ESTATE,
+ * MFQ_EDEVICE. */
+mfq_status mfq_get_slots(mfq_ctx *ctx, uint64_t *uid_host, int64_t *step_base_host);
+mfq_status mfq_set_slots(mfq_ctx *ctx, const uint64_t *uid_host, const int64_t *step_base_host);
+
 /* Wait for all work on the context's stream; reports deferred numeric errors
  * (MFQ_ENUMERIC) and clears them. */
 mfq_status mfq_synchronize(mfq_ctx *ctx);

@@ -1454,6 +1454,35 @@ mfq_status mfq_set_state(mfq_ctx *c, const void *U_host, int64_t step) {
   return MFQ_OK;
 }
 
+mfq_status mfq_get_slots(mfq_ctx *c, uint64_t *uid_host, int64_t *step_base_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!uid_host || !step_base_host) return fail(c, MFQ_EINVAL, "NULL output");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(uid_host, c->uid, (size_t)c->B * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream),
+         "uid download");
+  HIPCHK(hipMemcpyAsync(step_base_host, c->step_base, (size_t)c->B * sizeof(int64_t), hipMemcpyDeviceToHost,
+                        c->stream), "step base download");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return check_flag(c);
+}
+
+mfq_status mfq_set_slots(mfq_ctx *c, const uint64_t *uid_host, const int64_t *step_base_host) {
+  if (!c) return MFQ_EINVAL;
+  if (!c->ready) return fail(c, MFQ_ESTATE, "mfq_init_state has not succeeded");
+  if (!uid_host || !step_base_host) return fail(c, MFQ_EINVAL, "NULL input");
+  for (int b = 0; b < c->B; ++b)
+    if (step_base_host[b] < 0 || step_base_host[b] > c->step)
+      return fail(c, MFQ_EINVAL, "step base outside [0, step of the context]");
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  HIPCHK(hipMemcpyAsync(c->uid, uid_host, (size_t)c->B * sizeof(uint64_t), hipMemcpyHostToDevice, c->stream),
+         "uid upload");
+  HIPCHK(hipMemcpyAsync(c->step_base, step_base_host, (size_t)c->B * sizeof(int64_t), hipMemcpyHostToDevice,
+                        c->stream), "step base upload");
+  HIPCHK(hipStreamSynchronize(c->stream), "synchronize");
+  return MFQ_OK;
+}
+
 mfq_status mfq_synchronize(mfq_ctx *c) {
   if (!c) return MFQ_EINVAL;
   HIPCHK(hipSetDevice(c->device), "hipSetDevice");

@@ -91,6 +91,8 @@ _SIGS = {
     "mfq_set_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_get_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "mfq_set_state": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "mfq_get_slots": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mfq_set_slots": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_synchronize": (ctypes.c_int32, [ctypes.c_void_p]),
     "mfq_profile": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_use_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -545,6 +547,20 @@ class Trajectories:
 
     def set_state(self, U, step):
         mfq_set_state(self.ctx, U, step)
+
+    def get_slots(self):
+        """(uids, step bases) of the trajectories (mfq_get_slots)."""
+        uid = np.zeros(self.n_traj, dtype=np.uint64)
+        base = np.zeros(self.n_traj, dtype=np.int64)
+        _check(self.ctx, lib().mfq_get_slots(self.ctx, _ptr(uid), _ptr(base)))
+        return uid, base
+
+    def set_slots(self, uid, base):
+        """Restore (uids, step bases) from a checkpoint (mfq_set_slots)."""
+        u = np.ascontiguousarray(np.asarray(uid, dtype=np.uint64))
+        b = np.ascontiguousarray(np.asarray(base, dtype=np.int64))
+        _check(self.ctx, lib().mfq_set_slots(self.ctx, _ptr(u), _ptr(b)))
+        self.uids = [int(x) for x in u]
 
     def synchronize(self):
         mfq_synchronize(self.ctx)

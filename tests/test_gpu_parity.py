@@ -175,6 +175,39 @@ def test_checkpoint_roundtrip():
     b.close()
 
 
+def test_checkpoint_of_reset_slots_resumes_exactly():
+    """A slot refilled by mfq_reset_trajectory (new uid, own step count restarting) survives a
+    checkpoint: state, step, uids and step bases restored in a fresh context continue exactly
+    as the uninterrupted context, for both protocols, and the refilled slot draws as a fresh
+    trajectory of its uid (against the oracle)."""
+    L, dt, seed = 64, 0.05, 9
+    for proto, gam in ((QSD, [0.6, 1.1, 0.4]), (PM, [0.8, 1.5, 0.5])):
+        a = make_sim(1, L, n_traj=3, uids=[3, 4, 5])
+        a.step(proto, gam, dt, seed, 5)
+        a.reset_trajectory(1, 77)
+        a.step(proto, gam, dt, seed, 4)
+        U, n = a.get_state()
+        uid, base = a.get_slots()
+        assert list(uid) == [3, 77, 5] and list(base) == [0, 5, 0]
+        b = make_sim(1, L, n_traj=3, uids=[3, 4, 5])
+        b.set_state(U, n)
+        b.set_slots(uid, base)
+        a.step(proto, gam, dt, seed, 6)
+        b.step(proto, gam, dt, seed, 6)
+        Ua, _ = a.get_state()
+        Ub, _ = b.get_state()
+        assert np.array_equal(Ua, Ub)
+        # the refilled slot is a fresh trajectory of uid 77 after 10 of its own steps
+        ob = OracleBatch(1, L, 1, dt, [77])
+        for _ in range(10):
+            ob.step(proto, [gam[1]], seed)
+        assert np.abs(corr(Ub[1]) - corr(ob.U[0])).max() <= 1e-10
+        with pytest.raises(Exception):
+            b.set_slots(uid, [0, n + 100, 0])
+        a.close()
+        b.close()
+
+
 def test_all_site_projection_gives_zero_entropy():
     L = 32
     sim = make_sim(1, L, n_traj=2, uids=[0, 1])
