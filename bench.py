@@ -524,7 +524,7 @@ def run_served(args):
     seeded Poisson stream at `rate` jobs/s, per-job latency from arrival to completion."""
     from paper_2508_18468_amd import serve
     log(f"served_mix: {args.jobs} jobs at {args.rate} jobs/s, {args.job_steps} steps each")
-    r = serve.run(args.jobs, args.rate, args.job_steps, verbose=False)
+    r = serve.run(args.jobs, args.rate, args.job_steps, verbose=False, log=log)
     out = {"metric": "L*N*steps/s", "value": r["throughput_LNsteps_per_s"], "unit": "L*N*steps/s",
            "n_gpus": 1, "steps": args.job_steps, "warmup": 0, "ms_per_step": None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",

@@ -20,7 +20,9 @@ from . import mfq
 from .workloads import served_mix, HOMODYNE
 
 
-def run(n_jobs=64, rate=20.0, n_steps=500, budget_gb=200.0, max_slots=8, seed=1, verbose=False):
+def run(n_jobs=64, rate=20.0, n_steps=500, budget_gb=200.0, max_slots=8, seed=1, verbose=False, log=None):
+    """Serve the first n_jobs arrivals; `log` (a callable taking a line) reports each completion
+    as it is collected."""
     jobs = served_mix(n_jobs, rate, n_steps, seed)
     eng = mfq.Engine(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_slots=max_slots)
     t0 = time.perf_counter()
@@ -31,15 +33,33 @@ def run(n_jobs=64, rate=20.0, n_steps=500, budget_gb=200.0, max_slots=8, seed=1,
             time.sleep(delay)
         ids.append(eng.submit(j.dim, j.Lx, j.Ly, j.protocol, j.gamma, j.dt, j.n_steps, j.seed, j.uid,
                               j.region))
+        if log:
+            log(f"submitted job {j.job_id} at {time.perf_counter() - t0:.1f} s (L={j.L})")
     t_sub = time.perf_counter() - t0
     lat, work = [], 0.0
-    for j, i in zip(jobs, ids):
-        S, latency = eng.wait(i, timeout_s=3600.0)
-        lat.append(latency)
-        work += j.L * (j.L // 2) * j.n_steps
-        if verbose:
-            print(f"job {j.job_id}: L={j.L} proto={'qsd' if j.protocol == HOMODYNE else 'pm'} "
-                  f"gamma={j.gamma:.2f} S={S[-1]:.4f} latency={latency:.2f}s", flush=True)
+    pending = list(zip(jobs, ids))
+    deadline = time.perf_counter() + 3600.0
+    while pending:  # collect in completion order (each latency is the engine's own measure)
+        still = []
+        for j, i in pending:
+            r = eng.poll(i)
+            if r is None:
+                still.append((j, i))
+                continue
+            S, latency = r
+            lat.append(latency)
+            work += j.L * (j.L // 2) * j.n_steps
+            line = (f"job {j.job_id}: L={j.L} proto={'qsd' if j.protocol == HOMODYNE else 'pm'} "
+                    f"gamma={j.gamma:.2f} S={S[-1]:.4f} latency={latency:.2f}s")
+            if verbose:
+                print(line, flush=True)
+            if log:
+                log(line)
+        pending = still
+        if pending:
+            if time.perf_counter() > deadline:
+                raise TimeoutError(f"{len(pending)} jobs not done after an hour")
+            time.sleep(0.05)
     T = time.perf_counter() - t0
     st = eng.stats()
     eng.close()
