@@ -348,7 +348,7 @@ mfq_status mfq_propagator_band(mfq_ctx *ctx, int32_t *band);
  *                     step; such steps are not graph-replayed).  Needs N >= 128
  *                     and at most N measured sites in a step, else the step
  *                     falls back to the workgroup form;
- *   MFQ_PM_AUTO       blocked for L >= 2048, workgroup below (default). */
+ *   MFQ_PM_AUTO       blocked for N >= 128, workgroup below (default). */
 #define MFQ_PM_AUTO 0
 #define MFQ_PM_WORKGROUP 1
 #define MFQ_PM_BLOCKED 2

@@ -6,7 +6,9 @@
 // next job completion is nearest in work (shortest first, up to a combined
 // width that occupies the device), each in chunks of about CHUNK_TARGET_S of
 // wall time, up to the next observation or completion of one of its jobs,
-// after which finished slots are refilled from the queue.
+// after which finished slots are refilled from the queue.  Projective groups whose
+// steps synchronise the stream (the blocked measurement) are issued last, each from
+// a host thread of its own.
 // Each job keeps its own random numbers (key = (seed, uid), counter = its own
 // step index), so a job gives the same result alone and in any mix.  Groups of small
 // lattices (state, Gram and factor in one CU's LDS, FP64) are advanced together: up to
@@ -130,6 +132,16 @@ void worker_loop(mfq_engine *e) {
       std::vector<double> gam;
     };
     std::vector<Fused> fused;
+    // projective groups whose steps synchronise the stream inside mfq_step (blocked form)
+    struct Blocking {
+      int gid, k;
+      mfq_ctx *c;
+      ShapeKey key;
+      std::vector<double> gam;
+      double t_start = 0.0;
+      mfq_status st = MFQ_OK;
+    };
+    std::vector<Blocking> blocking;
     for (int gid : active) {
       std::unique_lock<std::mutex> lk(e->m);
       const Group &g = e->policy.group(gid);
@@ -143,6 +155,10 @@ void worker_loop(mfq_engine *e) {
       const int L = key.Lx * (key.dim == 2 ? key.Ly : 1);
       if (key.precision == MFQ_FP64 && mfq::fused_fits(L, key.N, key.Lx, key.dim == 2 ? key.Ly : 1)) {
         fused.push_back({gid, k, c, key, std::move(gam)});
+        continue;
+      }
+      if (key.protocol == MFQ_PROJECTIVE && key.N >= mfq::PM_BLOCKED_MIN_N) {
+        blocking.push_back({gid, k, c, key, std::move(gam)});
         continue;
       }
       const double t = e->now();
@@ -168,6 +184,19 @@ void worker_loop(mfq_engine *e) {
       const double t = e->now();
       const mfq_status st = mfq_run_group(cs.data(), as.data(), (int32_t)cs.size());
       for (size_t i = b0; i < b1; ++i) runs.push_back({fused[i].gid, fused[i].k, fused[i].c, t, st});
+    }
+    // the synchronising groups go last, each from a host thread of its own, so that their
+    // host round trips overlap one another and the groups already in flight
+    {
+      std::vector<std::thread> th;
+      th.reserve(blocking.size());
+      for (Blocking &b : blocking)
+        th.emplace_back([e, &b] {
+          b.t_start = e->now();
+          b.st = mfq_step(b.c, b.key.protocol, b.gam.data(), b.key.dt, b.key.seed, b.k);
+        });
+      for (std::thread &t : th) t.join();
+      for (const Blocking &b : blocking) runs.push_back({b.gid, b.k, b.c, b.t_start, b.st});
     }
     for (Run &r : runs) {
       mfq_status st = r.st != MFQ_OK ? r.st : mfq_synchronize(r.c);

@@ -16,6 +16,7 @@
 //   Householder tridiagonalisation, bisection, entropy sum; Sec. II).
 // Random numbers are the same Philox draws as the per-phase kernels, so the
 // two paths compute the same trajectory up to rounding.
+#include <atomic>
 #include <algorithm>
 
 #include "device_common.h"
@@ -321,8 +322,8 @@ __global__ __launch_bounds__(256) void fused_group_kernel(FusedGroup grp) {
 }
 
 hipError_t set_fused_lds_limit() {
-  static bool done = false;
-  if (done) return hipSuccess;
+  static std::atomic<bool> done{false};
+  if (done.load()) return hipSuccess;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fused_trajectory_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   if (e == hipSuccess)

@@ -114,6 +114,9 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
                       uint64_t seed, const uint64_t *uid, const int64_t *step_ptr, int step_offset,
                       const int64_t *step_base, const PmBlockedWork &w, bool *fallback,
                       hipStream_t s);
+// Smallest N for the blocked form (the Gram and T factor of a 64-wide WY block share
+// one N x N scratch).
+constexpr int PM_BLOCKED_MIN_N = 128;
 
 // ---------------------------------------------------------------- continuous-time protocol
 // Appendix A, PM protocol with Poisson waiting times: one event per active

@@ -339,7 +339,8 @@ hipError_t pm_blocked(cplx *U, cplx *scratch, int L, int N, int B, const double 
                       hipStream_t s) {
   hipError_t e;
   *fallback = false;
-  if (N < 2 * WY) {  // the Gram and T of a WY block share one N x N scratch
+  static_assert(PM_BLOCKED_MIN_N == 2 * WY, "the Gram and T of a WY block share one N x N scratch");
+  if (N < PM_BLOCKED_MIN_N) {
     *fallback = true;
     return hipSuccess;
   }
