@@ -15,7 +15,10 @@ L = 16384 ring with the dense FP64 propagator (the propagator GEMM the 50 %-of-p
 stated on), the 384-trajectory L = 1024 ring batch, and the CPU oracle on a bounded sample.
 
 Other workloads: --workload ring1024_qsd | ring16384_pm | ring16384_qsd | ring1024_pm_ct |
-served_mix.  Prints one JSON line.
+served_mix.  served_mix submits the first --jobs arrivals of a seeded Poisson stream at --rate
+jobs/s to the continuous-batching engine (default 32 at 0.25 jobs/s, a load the engine keeps up
+with) and reports throughput beside the measured per-job latency distribution (p50, p99).
+Prints one JSON line.
 """
 
 import argparse
@@ -564,8 +567,10 @@ def main():
                     help="large ring workloads: dense GEMM (default) or banded form")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_bulk"],
                     help="large ring workloads (default fp64)")
-    ap.add_argument("--jobs", type=int, default=64, help="served_mix: arrivals")
-    ap.add_argument("--rate", type=float, default=20.0, help="served_mix: mean arrivals per second")
+    ap.add_argument("--jobs", type=int, default=32, help="served_mix: arrivals")
+    ap.add_argument("--rate", type=float, default=0.25,
+                    help="served_mix: mean arrivals per second (0.25: a load the engine sustains; "
+                         "20: the overload window)")
     ap.add_argument("--job-steps", type=int, default=500, help="served_mix: steps per job")
     args = ap.parse_args()
     if args.summarize_pmc:

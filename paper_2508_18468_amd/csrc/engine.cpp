@@ -5,10 +5,12 @@
 // groups' steps overlap on the device.  Each round advances the groups whose
 // next job completion is nearest in work (shortest first, up to a combined
 // width that occupies the device), each in chunks of about CHUNK_TARGET_S of
-// wall time, up to the next observation or completion of one of its jobs,
-// after which finished slots are refilled from the queue.  Projective groups whose
-// steps synchronise the stream (the blocked measurement) are issued last, each from
-// a host thread of its own.
+// wall time (or of the slowest step in the round, which the round lasts anyway),
+// up to the next observation or completion of one of its jobs, after which
+// finished slots are refilled from the queue.  A group's step cost is measured
+// by events on its stream; a new group first advances a short probe chunk.
+// Projective groups whose steps synchronise the stream (the blocked
+// measurement) are issued last, each from a host thread of its own.
 // Each job keeps its own random numbers (key = (seed, uid), counter = its own
 // step index), so a job gives the same result alone and in any mix.  Groups of small
 // lattices (state, Gram and factor in one CU's LDS, FP64) are advanced together: up to
@@ -28,11 +30,28 @@ using namespace mfq_serving;
 
 namespace {
 constexpr double CHUNK_TARGET_S = 0.02;
-constexpr int CHUNK_MAX = 64;
+constexpr int CHUNK_MAX = 256;
 // Groups advanced together hold at least this many state elements (L * N per
 // trajectory): 128 x 128-tile propagator products of ~2000 workgroups.
 constexpr double WIDTH_BUDGET = 32.0 * 1024 * 1024;
+
+// Device resources of one batch group: its library context, the stream it runs on and two
+// events that time each chunk on that stream (the time a chunk took on the shared device,
+// whatever order the worker collects the groups in).
+struct GroupRes {
+  mfq_ctx *c = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+void release(GroupRes &r) {
+  if (r.c) mfq_destroy(r.c);
+  if (r.e0) (void)hipEventDestroy(r.e0);
+  if (r.e1) (void)hipEventDestroy(r.e1);
+  if (r.s) (void)hipStreamDestroy(r.s);
+  r = GroupRes{};
 }
+}  // namespace
 
 struct mfq_engine {
   int device = 0;
@@ -41,7 +60,7 @@ struct mfq_engine {
   std::condition_variable cv;
   std::thread worker;
   bool stop = false;
-  std::map<int, mfq_ctx *> ctx_of_group;
+  std::map<int, GroupRes> res_of_group;
   std::string err;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   mfq_engine(int dev, size_t budget, int max_slots, Policy::BytesFn f)
@@ -69,7 +88,23 @@ size_t footprint(const ShapeKey &k, int cap) {
   return b;
 }
 
+mfq_status create_group(int device, const Group &g, GroupRes &r) {
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&r.s) != hipSuccess ||
+      hipEventCreate(&r.e0) != hipSuccess || hipEventCreate(&r.e1) != hipSuccess) {
+    release(r);
+    return MFQ_EDEVICE;
+  }
+  mfq_lattice l = lattice_of(g.key);
+  std::vector<uint64_t> uids(g.capacity, 0);
+  mfq_status st = mfq_create(device, r.s, &r.c);
+  if (st == MFQ_OK)
+    st = mfq_init_state(r.c, &l, g.key.N, g.capacity, uids.data(), nullptr, g.key.precision, nullptr, 0);
+  if (st != MFQ_OK) release(r);
+  return st;
+}
+
 void worker_loop(mfq_engine *e) {
+  (void)hipSetDevice(e->device);
   while (true) {
     std::vector<Action> actions;
     {
@@ -81,34 +116,29 @@ void worker_loop(mfq_engine *e) {
       std::unique_lock<std::mutex> lk(e->m);
       const Group &g = e->policy.group(a.group);
       if (a.kind == Action::DESTROY) {
-        auto it = e->ctx_of_group.find(a.group);
-        if (it != e->ctx_of_group.end()) {
-          mfq_destroy(it->second);
-          e->ctx_of_group.erase(it);
+        auto it = e->res_of_group.find(a.group);
+        if (it != e->res_of_group.end()) {
+          release(it->second);
+          e->res_of_group.erase(it);
         }
       } else if (a.kind == Action::CREATE) {
-        mfq_ctx *c = nullptr;
-        mfq_lattice l = lattice_of(g.key);
-        std::vector<uint64_t> uids(g.capacity, 0);
-        mfq_status st = mfq_create(e->device, nullptr, &c);
-        if (st == MFQ_OK)
-          st = mfq_init_state(c, &l, g.key.N, g.capacity, uids.data(), nullptr, g.key.precision,
-                              nullptr, 0);
+        GroupRes r;
+        const mfq_status st = create_group(e->device, g, r);
         if (st != MFQ_OK) {
-          if (c) mfq_destroy(c);
           e->policy.group_failed(a.group, st);
         } else {
-          e->ctx_of_group[a.group] = c;
+          e->res_of_group[a.group] = r;
           e->policy.group_created(a.group);
         }
       } else {  // ADMIT
-        auto it = e->ctx_of_group.find(a.group);
+        auto it = e->res_of_group.find(a.group);
         const Job *j = e->policy.job(a.job);
-        if (it != e->ctx_of_group.end() && j)
-          mfq_reset_trajectory(it->second, a.slot, j->uid);
+        if (it != e->res_of_group.end() && j)
+          mfq_reset_trajectory(it->second.c, a.slot, j->uid);
       }
     }
     std::vector<int> active;
+    double target = CHUNK_TARGET_S;
     {
       std::unique_lock<std::mutex> lk(e->m);
       active = e->policy.schedule(WIDTH_BUDGET);
@@ -116,63 +146,60 @@ void worker_loop(mfq_engine *e) {
         e->cv.wait_for(lk, std::chrono::milliseconds(5));
         continue;
       }
+      target = e->policy.round_target(active, CHUNK_TARGET_S);
     }
-    // enqueue one chunk per group (each group on its own stream), then collect
+    // one chunk per group, each on its own stream between its two events; then collect
     struct Run {
       int gid, k;
-      mfq_ctx *c;
-      double t_start;
+      GroupRes r;
+      double t_start;  // host clock at issue (fallback timing)
       mfq_status st;
+      const GroupRes *timer;  // whose events bracket this run (fused runs share the first's)
     };
     std::vector<Run> runs;
-    struct Fused {
+    struct Pending {
       int gid, k;
-      mfq_ctx *c;
+      GroupRes r;
       ShapeKey key;
       std::vector<double> gam;
-    };
-    std::vector<Fused> fused;
-    // projective groups whose steps synchronise the stream inside mfq_step (blocked form)
-    struct Blocking {
-      int gid, k;
-      mfq_ctx *c;
-      ShapeKey key;
-      std::vector<double> gam;
-      double t_start = 0.0;
       mfq_status st = MFQ_OK;
     };
-    std::vector<Blocking> blocking;
+    std::vector<Pending> fused, blocking;
     for (int gid : active) {
       std::unique_lock<std::mutex> lk(e->m);
       const Group &g = e->policy.group(gid);
-      const int k = e->policy.chunk(gid, CHUNK_TARGET_S, CHUNK_MAX);
+      const int k = e->policy.chunk(gid, target, CHUNK_MAX);
       std::vector<double> gam(g.capacity, 0.0);
       for (int s = 0; s < g.capacity; ++s)
         if (g.slot_job[s] >= 0) gam[s] = e->policy.job((uint64_t)g.slot_job[s])->gamma;
-      mfq_ctx *c = e->ctx_of_group[gid];
+      const GroupRes r = e->res_of_group[gid];
       const ShapeKey key = g.key;
       lk.unlock();
       const int L = key.Lx * (key.dim == 2 ? key.Ly : 1);
       if (key.precision == MFQ_FP64 && mfq::fused_fits(L, key.N, key.Lx, key.dim == 2 ? key.Ly : 1)) {
-        fused.push_back({gid, k, c, key, std::move(gam)});
+        fused.push_back({gid, k, r, key, std::move(gam)});
         continue;
       }
+      // projective steps in the blocked form synchronise their stream inside mfq_step
       if (key.protocol == MFQ_PROJECTIVE && key.N >= mfq::PM_BLOCKED_MIN_N) {
-        blocking.push_back({gid, k, c, key, std::move(gam)});
+        blocking.push_back({gid, k, r, key, std::move(gam)});
         continue;
       }
       const double t = e->now();
-      mfq_status st = mfq_step(c, key.protocol, gam.data(), key.dt, key.seed, k);
-      runs.push_back({gid, k, c, t, st});
+      (void)hipEventRecord(r.e0, r.s);
+      const mfq_status st = mfq_step(r.c, key.protocol, gam.data(), key.dt, key.seed, k);
+      (void)hipEventRecord(r.e1, r.s);
+      runs.push_back({gid, k, r, t, st, nullptr});
     }
-    // small lattices: one fused launch per (up to) FUSED_GROUP_MAX groups
+    // small lattices: one fused launch per (up to) FUSED_GROUP_MAX groups, on the first
+    // group's stream
     for (size_t b0 = 0; b0 < fused.size(); b0 += mfq::FUSED_GROUP_MAX) {
       const size_t b1 = std::min(fused.size(), b0 + (size_t)mfq::FUSED_GROUP_MAX);
       std::vector<mfq_ctx *> cs;
       std::vector<mfq_run_args> as;
       for (size_t i = b0; i < b1; ++i) {
-        const Fused &f = fused[i];
-        cs.push_back(f.c);
+        const Pending &f = fused[i];
+        cs.push_back(f.r.c);
         mfq_run_args a{};
         a.protocol = f.key.protocol;
         a.gamma = f.gam.data();
@@ -181,32 +208,44 @@ void worker_loop(mfq_engine *e) {
         a.n_steps = f.k;
         as.push_back(a);
       }
+      const GroupRes &lead = fused[b0].r;
       const double t = e->now();
+      (void)hipEventRecord(lead.e0, lead.s);
       const mfq_status st = mfq_run_group(cs.data(), as.data(), (int32_t)cs.size());
-      for (size_t i = b0; i < b1; ++i) runs.push_back({fused[i].gid, fused[i].k, fused[i].c, t, st});
+      (void)hipEventRecord(lead.e1, lead.s);
+      for (size_t i = b0; i < b1; ++i) runs.push_back({fused[i].gid, fused[i].k, fused[i].r, t, st, &fused[b0].r});
     }
     // the synchronising groups go last, each from a host thread of its own, so that their
     // host round trips overlap one another and the groups already in flight
     {
       std::vector<std::thread> th;
+      std::vector<double> t0(blocking.size());
       th.reserve(blocking.size());
-      for (Blocking &b : blocking)
-        th.emplace_back([e, &b] {
-          b.t_start = e->now();
-          b.st = mfq_step(b.c, b.key.protocol, b.gam.data(), b.key.dt, b.key.seed, b.k);
+      for (size_t i = 0; i < blocking.size(); ++i)
+        th.emplace_back([e, &blocking, &t0, i] {
+          Pending &b = blocking[i];
+          (void)hipSetDevice(e->device);
+          t0[i] = e->now();
+          (void)hipEventRecord(b.r.e0, b.r.s);
+          b.st = mfq_step(b.r.c, b.key.protocol, b.gam.data(), b.key.dt, b.key.seed, b.k);
+          (void)hipEventRecord(b.r.e1, b.r.s);
         });
       for (std::thread &t : th) t.join();
-      for (const Blocking &b : blocking) runs.push_back({b.gid, b.k, b.c, b.t_start, b.st});
+      for (size_t i = 0; i < blocking.size(); ++i)
+        runs.push_back({blocking[i].gid, blocking[i].k, blocking[i].r, t0[i], blocking[i].st, nullptr});
     }
     for (Run &r : runs) {
-      mfq_status st = r.st != MFQ_OK ? r.st : mfq_synchronize(r.c);
-      const double t_end = e->now();
+      mfq_status st = r.st != MFQ_OK ? r.st : mfq_synchronize(r.r.c);
+      const GroupRes &tm = r.timer ? *r.timer : r.r;
+      float ms = 0.0f;
+      double wall = e->now() - r.t_start;
+      if (st == MFQ_OK && hipEventElapsedTime(&ms, tm.e0, tm.e1) == hipSuccess) wall = 1e-3 * ms;
       std::unique_lock<std::mutex> lk(e->m);
       if (st != MFQ_OK) {
-        e->policy.fail_group_jobs(r.gid, st, t_end);
+        e->policy.fail_group_jobs(r.gid, st, e->now());
         continue;
       }
-      std::vector<uint64_t> obs = e->policy.advanced(r.gid, r.k, t_end - r.t_start);
+      std::vector<uint64_t> obs = e->policy.advanced(r.gid, r.k, wall);
       const Group &g = e->policy.group(r.gid);
       // one entropy call per distinct region among the observing jobs
       std::vector<double> S(g.capacity, 0.0);
@@ -216,7 +255,7 @@ void worker_loop(mfq_engine *e) {
         const Job *ja = e->policy.job(obs[a]);
         const std::vector<int> region = ja->region;
         lk.unlock();
-        st = mfq_entropy(r.c, region.data(), (int32_t)region.size(), S.data());
+        st = mfq_entropy(r.r.c, region.data(), (int32_t)region.size(), S.data());
         lk.lock();
         if (st != MFQ_OK) {
           e->policy.fail_group_jobs(r.gid, st, e->now());
@@ -258,7 +297,7 @@ mfq_status mfq_engine_destroy(mfq_engine *e) {
   }
   e->cv.notify_all();
   if (e->worker.joinable()) e->worker.join();
-  for (auto &kv : e->ctx_of_group) mfq_destroy(kv.second);
+  for (auto &kv : e->res_of_group) release(kv.second);
   delete e;
   return MFQ_OK;
 }

@@ -193,9 +193,12 @@ class Policy {
 
   // Steps for group g to advance now: up to the next observation or
   // completion of any of its jobs, and about target_s of wall time.
+  // A group whose step cost is not yet known advances PROBE_STEPS steps (one captured
+  // step pair), so that a first chunk never holds a round for long.
+  static constexpr int PROBE_STEPS = 2;
   int chunk(int gid, double target_s, int max_chunk) const {
     const Group &g = groups_[gid];
-    int k = max_chunk;
+    int k = std::min(max_chunk, PROBE_STEPS);
     if (g.step_cost_s > 0.0) k = std::max(1, std::min(max_chunk, (int)(target_s / g.step_cost_s)));
     for (int64_t jid : g.slot_job) {
       if (jid < 0) continue;
@@ -205,6 +208,15 @@ class Policy {
       k = std::min(k, std::max(1, next));
     }
     return k;
+  }
+
+  // Wall time of a round that advances groups gids: every group takes at least one step,
+  // so the round lasts at least the slowest known step; the others then fill that time
+  // (at least target_s).
+  double round_target(const std::vector<int> &gids, double target_s) const {
+    double t = target_s;
+    for (int gid : gids) t = std::max(t, groups_[gid].step_cost_s);
+    return t;
   }
 
   // Group gid advanced by k steps: returns the jobs that reached an

@@ -18,12 +18,13 @@
 //   128 x 128, 8 waves, 64 x 32 per wave   the large ones: half the L2->CU
 //              bytes per flop of the small tile, 64 accumulator doubles per
 //              lane (more per wave would overflow the register file).
-// K advances in chunks of 16 through one LDS buffer; the next chunk is fetched
-// into registers while the current one feeds the matrix cores, then stored
-// between two barriers.  A single buffer (66 KiB for 128 x 128 tiles) lets two
-// workgroups share a compute unit, one computing while the other waits at a
-// barrier; the reduction epilogues, which reuse the operand LDS as scratch, keep
-// two buffers.
+// K advances in chunks of 16; the next chunk is fetched into registers while the
+// current one feeds the matrix cores.  Products with op(A) = A (the propagator among
+// them) store it into their one LDS buffer between two barriers (66 KiB for
+// 128 x 128 tiles, whose ~208 VGPRs per lane allow one 512-thread workgroup per
+// compute unit); the Gram-shaped products (op(A) = A^+) and the reduction
+// epilogues keep two buffers, store the next chunk after the first MFMA k-step of the
+// current one and pass one barrier per chunk.
 //
 // Workgroup -> tile mapping is XCD-aware: the dispatcher hands workgroup i to
 // XCD i mod 8, so the 1-D grid is ordered such that all tiles of one batch
@@ -202,7 +203,11 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   if (g.aUpper) kbeg = (m0 / KT) * KT;
   if (g.bUpper) kend = min(g.K, n0 + NT);
 
-  constexpr int NBUF = (FL & (FL_SQSUM | FL_DIAG)) != 0 ? 2 : 1;
+  // Two buffers for the Gram-shaped products (op(A) = A^+) and the reduction epilogues: the
+  // next chunk is stored into the idle buffer after the current one's first k-step, and one
+  // barrier per chunk remains (Gram U^+U at L = 1024, N = 512, 384 trajectories: 0.667 ->
+  // 0.695 of the FP64 peak).  The propagator product gains nothing from it and keeps one.
+  constexpr int NBUF = ((FL & (FL_SQSUM | FL_DIAG)) != 0 || OPA == OP_C) ? 2 : 1;
   __shared__ double Ar[NBUF][KT][MT + PAD], Ai[NBUF][KT][MT + PAD];
   __shared__ double Br[NBUF][KT][NT + PAD], Bi[NBUF][KT][NT + PAD];
 
@@ -303,6 +308,8 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
     if (it + 1 < nk) load(kbeg + (it + 1) * KT);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
+      // the idle buffer was last read in the previous chunk, before its closing barrier
+      if (NBUF == 2 && kk == 4 && it + 1 < nk) store(buf ^ 1);
       const int k = kk + (lane >> 4);
       double a_re[IM], a_im[IM], b_re[JN], b_im[JN];
 #pragma unroll
@@ -334,8 +341,10 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
         }
       }
     }
-    if (NBUF == 1) __syncthreads();  // every wave is done with the buffer
-    if (it + 1 < nk) store(NBUF == 2 ? (buf ^ 1) : 0);
+    if (NBUF == 1) {
+      __syncthreads();  // every wave is done with the buffer
+      if (it + 1 < nk) store(0);
+    }
     __syncthreads();
   }
 

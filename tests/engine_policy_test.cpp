@@ -81,6 +81,8 @@ int main() {
     CHECK(creates == 1);  // capacity 2: a and b share a group, c waits for a slot
     CHECK(p.job(a)->state == ACTIVE && p.job(b)->state == ACTIVE && p.job(c)->state == QUEUED);
     const int g = p.job(a)->group;
+    CHECK(p.chunk(g, 1.0, 1000) == Policy::PROBE_STEPS);  // step cost unknown: a probe chunk
+    CHECK(p.advanced(g, Policy::PROBE_STEPS, 0.01).empty());
     for (uint64_t jid : p.advanced(g, p.chunk(g, 1.0, 1000), 0.01)) {
       const Job *j = p.job(jid);
       if (j->steps_done >= j->n_steps) p.complete(jid, 1.0);
@@ -103,6 +105,7 @@ int main() {
     auto acts = p.plan();
     for (auto &x : acts) if (x.kind == Action::CREATE) p.group_created(x.group);
     const int g = p.job(small1)->group;
+    p.advanced(g, p.chunk(g, 1.0, 1000), 0.01);  // the probe chunk
     for (uint64_t jid : p.advanced(g, p.chunk(g, 1.0, 1000), 0.01))
       if (p.job(jid)->steps_done >= p.job(jid)->n_steps) p.complete(jid, 1.0);
     CHECK(p.job(small1b)->state == DONE);
@@ -171,6 +174,24 @@ int main() {
     p.complete(tiny_late, 1.0);
     std::vector<int> after = p.schedule(1e30);
     CHECK(after.size() == 3 && after[0] == gs && after[1] == gb && after[2] == gm);
+  }
+  {  // chunk sizes: a probe first, then about the round's wall time, never past a completion
+    Policy p(1 << 30, 2, fake_bytes);
+    const uint64_t fast = p.submit(job(64, 1000)), slow = p.submit(job(256, 1000));
+    for (auto &x : p.plan()) if (x.kind == Action::CREATE) p.group_created(x.group);
+    const int gf = p.job(fast)->group, gs = p.job(slow)->group;
+    CHECK(p.chunk(gf, 0.02, 256) == Policy::PROBE_STEPS && p.chunk(gs, 0.02, 256) == Policy::PROBE_STEPS);
+    CHECK(p.round_target({gf, gs}, 0.02) == 0.02);  // no cost known yet
+    p.advanced(gf, 2, 0.002);                        // 1 ms per step
+    p.advanced(gs, 2, 0.2);                          // 100 ms per step
+    const double T = p.round_target({gf, gs}, 0.02);
+    CHECK(T > 0.0999 && T < 0.1001);                 // the slow group's one step sets the round
+    CHECK(p.chunk(gs, T, 256) == 1);
+    CHECK(p.chunk(gf, T, 256) == 100);               // the fast group fills that time
+    CHECK(p.chunk(gf, T, 64) == 64);                 // within the chunk cap
+    CHECK(p.round_target({gf}, 0.02) == 0.02);
+    p.advanced(gf, 995, 0.995);
+    CHECK(p.chunk(gf, T, 256) == 3);                 // stops at the job's last step
   }
   std::printf(failures ? "policy checks: %d failures\n" : "policy checks: all passed\n", failures);
   return failures ? 1 : 0;
