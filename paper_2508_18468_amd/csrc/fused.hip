@@ -60,9 +60,16 @@ __host__ __device__ inline FusedLayout fused_layout(int L, int N, int Lx, int Ly
 // independent partial sums per entry, right-looking Cholesky in one wave, then
 // the triangular solve Y R = X (Y overwrites X) one row per thread.  A non-positive or
 // non-finite pivot sets *bad to its column + 1 and *bad_pivot to its value (first one only).
+// With certify, X is kept as it is when its Gram is within CHOL_KEEP_MAX of the identity
+// entrywise (|Re| + |Im| of G - I), as the second pass of the per-phase path does.
 __device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu, int lg, int *bad,
-                           double *bad_pivot) {
+                           double *bad_pivot, bool certify) {
   const int tid = threadIdx.x;
+  // largest deviation as the bit pattern of a non-negative double (NaN orders above all)
+  __shared__ unsigned long long dev_bits;
+  if (tid == 0) dev_bits = 0ull;
+  __syncthreads();
+  double dmax = 0.0;
   for (int idx = tid; idx < N * N; idx += 256) {
     const int a = idx % N, c = idx / N;
     if (a > c) continue;
@@ -82,9 +89,14 @@ __device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu
       sr[0] += p.re * q.re + p.im * q.im;
       si[0] += p.re * q.im - p.im * q.re;
     }
-    G[a + c * lg] = cplx{(sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3])};
+    const cplx gac{(sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3])};
+    G[a + c * lg] = gac;
+    const double dv = fabs(a == c ? gac.re - 1.0 : gac.re) + fabs(gac.im);
+    dmax = (dv != dv || dmax != dmax) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(dmax, dv);
   }
+  if (certify) atomicMax(&dev_bits, (unsigned long long)__double_as_longlong(dmax));
   __syncthreads();  // the Gram is written by every wave
+  if (certify && __longlong_as_double((long long)dev_bits) <= CHOL_KEEP_MAX) return;
   // Cholesky by wave 0 alone: lanes of one wave run in lockstep, so the
   // column steps need only wave-level ordering, not workgroup barriers
   if (tid < 64) {
@@ -236,8 +248,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
                                   lu);
       __syncthreads();
     }
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot);
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot);
+    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot, false);
+    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot, true);
     // state now in Ub: swap so that it is in Ua for the next step
     cplx *t = Ua;
     Ua = Ub;
