@@ -379,29 +379,50 @@ mfq_status mfq_set_eig_path(mfq_ctx *ctx, int32_t path);
 #define MFQ_TILE_SMALL 1  /* always 64 x 64 (4 waves) */
 #define MFQ_TILE_LARGE 2  /* 128 x 128 (8 waves) whenever every dimension is >= 128 */
 
+/* Workgroup -> tile order of the GEMMs (mfq_set_tile_order): XCD groups all tiles of one
+ * batch entry (or one column panel of a single wide product) on one XCD so that they share
+ * its L2; LINEAR hands tile i to workgroup i.  Results are bitwise the same either way. */
+#define MFQ_ORDER_XCD 0
+#define MFQ_ORDER_LINEAR 1
+
+#define MFQ_TUNE_MAX_CANDIDATES 16
+
 /* Result of mfq_autotune. */
 typedef struct {
   int32_t path;             /* chosen mfq_run path: MFQ_PATH_FUSED or MFQ_PATH_LAUNCHES */
   int32_t tile;             /* chosen MFQ_TILE_* */
   double ms_per_step;       /* wall time per step of the chosen configuration */
-  int32_t n_candidates;     /* entries used in candidate_ms */
+  int32_t n_candidates;     /* entries used in the candidate arrays */
+  int32_t order;            /* chosen MFQ_ORDER_* */
+  int32_t pm_path;          /* chosen MFQ_PM_* (the context's setting when not searched) */
   int32_t reserved;
-  double candidate_ms[8];   /* ms per step of: launches x {AUTO, SMALL, LARGE}, then fused (if
-                               the problem fits in LDS) */
+  double candidate_ms[MFQ_TUNE_MAX_CANDIDATES];   /* ms per step of each candidate probed */
+  int32_t cand_path[MFQ_TUNE_MAX_CANDIDATES];     /* its path, */
+  int32_t cand_tile[MFQ_TUNE_MAX_CANDIDATES];     /* tile, */
+  int32_t cand_order[MFQ_TUNE_MAX_CANDIDATES];    /* tile order */
+  int32_t cand_pm[MFQ_TUNE_MAX_CANDIDATES];       /* and projective form */
 } mfq_tuning;
 
 /* Autotuner of the execution form of a step (the batched launch of the hot
  * path): times probe_steps steps of the given protocol and parameters under
- * every candidate (per-phase launches with each GEMM tile choice, and the fused
- * LDS-resident kernel when the problem fits), each after one warm-up run, and
- * keeps the fastest as the context's path (for mfq_run) and tile choice (for
- * every call).  The state, the step index and the events of the last step are
- * saved before and restored after the probes, so tuning does not change any
- * trajectory.  Allocates a temporary device copy of the state.  Synchronises.
- * Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_ENOMEM / MFQ_EDEVICE, or the first error a
- * probe reports (the previous choice is then kept). */
+ * each candidate, after one warm-up run (a candidate whose warm-up takes ten
+ * times the best time so far is not timed again), coordinate by coordinate:
+ * for projective steps with N >= 128 the measurement form (blocked or one
+ * workgroup per trajectory), then with that form every GEMM tile size (AUTO,
+ * SMALL, LARGE) in both tile orders (MFQ_ORDER_*), then the fused
+ * LDS-resident kernel when the problem fits.  The fastest becomes the
+ * context's path (for mfq_run), tile size and order (for every call) and
+ * projective form.  The state, the step index and the events of the last step
+ * are saved before and restored after the probes, so tuning does not change
+ * any trajectory.  Allocates a temporary device copy of the state.
+ * Synchronises.  Errors: MFQ_EINVAL, MFQ_ESTATE, MFQ_ENOMEM / MFQ_EDEVICE, or
+ * the first error a probe reports (the previous choice is then kept). */
 mfq_status mfq_autotune(mfq_ctx *ctx, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                         int32_t probe_steps, mfq_tuning *out);
+
+/* Tile order of the context's GEMMs (MFQ_ORDER_XCD default, or MFQ_ORDER_LINEAR).
+ * Errors: MFQ_EINVAL for another value. */
+mfq_status mfq_set_tile_order(mfq_ctx *ctx, int32_t order);
 
 /* Apply a previously tuned choice (e.g. from a cache) without probing. */
 mfq_status mfq_set_tuning(mfq_ctx *ctx, int32_t path, int32_t tile);

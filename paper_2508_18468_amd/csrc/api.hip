@@ -111,11 +111,13 @@ struct mfq_ctx {
   // mfq_run: execution path and its observation buffer; GEMM tile choice
   int run_path = 0;   // MFQ_PATH_AUTO
   int tile_mode = 0;  // MFQ_TILE_AUTO
+  int tile_order = 0;  // MFQ_ORDER_XCD
   int eig_mode = 0;   // MFQ_EIG_AUTO
   // correlation observables: tile partials and results (allocated on first use)
   double *red_buf = nullptr;
   size_t red_cap = 0;
   int g_tile = -1;    // tile choice the cached graph was captured with
+  int g_order = -1;   // tile order the cached graph was captured with
   double *run_S = nullptr;
   size_t run_S_cap = 0;
 };
@@ -509,13 +511,16 @@ mfq_status enqueue_step(mfq_ctx *c, int protocol, double dt, uint64_t seed, int 
 
 // The context's GEMM tile choice and reduction form for the launches of one ABI call.
 struct TileScope {
-  int saved, saved_eig;
-  explicit TileScope(const mfq_ctx *c) : saved(gemm_tile_mode()), saved_eig(eig_path()) {
+  int saved, saved_order, saved_eig;
+  explicit TileScope(const mfq_ctx *c)
+      : saved(gemm_tile_mode()), saved_order(gemm_tile_order()), saved_eig(eig_path()) {
     set_gemm_tile_mode(c->tile_mode);
+    set_gemm_tile_order(c->tile_order);
     set_eig_path(c->eig_mode);
   }
   ~TileScope() {
     set_gemm_tile_mode(saved);
+    set_gemm_tile_order(saved_order);
     set_eig_path(saved_eig);
   }
 };
@@ -532,7 +537,8 @@ void drop_graph(mfq_ctx *c) {
 // parity change.  Replayed with hipGraphLaunch for each pair of steps.
 mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed) {
   if (c->gexec && c->g_protocol == protocol && c->g_dt == dt && c->g_seed == seed && c->g_cur == c->cur &&
-      c->g_tile == c->tile_mode && c->g_prop == c->prop_form && c->g_integ == c->integrator)
+      c->g_tile == c->tile_mode && c->g_order == c->tile_order && c->g_prop == c->prop_form &&
+      c->g_integ == c->integrator)
     return MFQ_OK;
   drop_graph(c);
   const int cur0 = c->cur;
@@ -556,6 +562,7 @@ mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed)
   c->g_seed = seed;
   c->g_cur = cur0;
   c->g_tile = c->tile_mode;
+  c->g_order = c->tile_order;
   c->g_prop = c->prop_form;
   c->g_integ = c->integrator;
   return MFQ_OK;
@@ -1228,6 +1235,14 @@ mfq_status mfq_set_tuning(mfq_ctx *c, int32_t path, int32_t tile) {
   return MFQ_OK;
 }
 
+mfq_status mfq_set_tile_order(mfq_ctx *c, int32_t order) {
+  if (!c) return MFQ_EINVAL;
+  if (order != MFQ_ORDER_XCD && order != MFQ_ORDER_LINEAR) return fail(c, MFQ_EINVAL, "unknown tile order");
+  c->tile_order = order;
+  drop_graph(c);
+  return MFQ_OK;
+}
+
 mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, double dt, uint64_t seed,
                         int32_t probe_steps, mfq_tuning *out) {
   if (!c) return MFQ_EINVAL;
@@ -1258,7 +1273,6 @@ mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, doubl
   };
   const int cur0 = c->cur;
   const int64_t step0 = c->step;
-  const int path0 = c->run_path, tile0 = c->tile_mode;
   hipError_t he = hipMemcpyAsync(save, c->X[cur0], ubytes, hipMemcpyDeviceToDevice, c->stream);
   if (he == hipSuccess) he = copy_events(true);
   auto restore = [&]() -> hipError_t {
@@ -1268,19 +1282,21 @@ mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, doubl
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     return e;
   };
-  struct Cand { int path, tile; };
-  std::vector<Cand> cands = {{MFQ_PATH_LAUNCHES, MFQ_TILE_AUTO},
-                             {MFQ_PATH_LAUNCHES, MFQ_TILE_SMALL},
-                             {MFQ_PATH_LAUNCHES, MFQ_TILE_LARGE}};
-  const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
-  if (fused_fits(c->L, c->N, c->lat.Lx, Ly) && !(protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4))
-    cands.push_back({MFQ_PATH_FUSED, MFQ_TILE_AUTO});
+  // Candidates, searched coordinate by coordinate: the projective measurement form first (when
+  // both apply), then GEMM tile size x tile order with that form, then the fused kernel.
+  struct Cand { int path, tile, order, pm; };
+  const int path0 = c->run_path, tile0 = c->tile_mode, order0 = c->tile_order, pm0 = c->pm_path;
   std::memset(out, 0, sizeof(*out));
-  int best = -1;
+  int n = 0;
   double best_ms = 0.0;
-  for (size_t i = 0; i < cands.size() && he == hipSuccess && st == MFQ_OK; ++i) {
-    c->run_path = cands[i].path;
-    c->tile_mode = cands[i].tile;
+  Cand best{path0, tile0, order0, pm0};
+  bool have_best = false;
+  auto probe = [&](const Cand &k) {
+    if (he != hipSuccess || st != MFQ_OK || n >= MFQ_TUNE_MAX_CANDIDATES) return;
+    c->run_path = k.path;
+    c->tile_mode = k.tile;
+    c->tile_order = k.order;
+    c->pm_path = k.pm;
     double ms = 0.0;
     for (int rep = 0; rep < 2 && he == hipSuccess && st == MFQ_OK; ++rep) {  // warm-up, then timed
       if ((he = restore()) != hipSuccess) break;
@@ -1288,34 +1304,68 @@ mfq_status mfq_autotune(mfq_ctx *c, int32_t protocol, const double *gamma, doubl
       const auto t0 = std::chrono::steady_clock::now();
       st = mfq_run(c, protocol, gamma, dt, seed, probe_steps, 0, nullptr, 0, nullptr, &n_obs);
       ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      // a warm-up ten times slower than the best so far is not worth a timed run
+      if (rep == 0 && have_best && ms > 10.0 * best_ms) break;
     }
-    out->candidate_ms[i] = ms / probe_steps;
-    if (st == MFQ_OK && (best < 0 || ms < best_ms)) {
-      best = (int)i;
+    out->candidate_ms[n] = ms / probe_steps;
+    out->cand_path[n] = k.path;
+    out->cand_tile[n] = k.tile;
+    out->cand_order[n] = k.order;
+    out->cand_pm[n] = k.pm;
+    ++n;
+    if (st == MFQ_OK && (!have_best || ms < best_ms)) {
+      best = k;
       best_ms = ms;
+      have_best = true;
     }
+  };
+  int pm = pm0;
+  if (protocol == MFQ_PROJECTIVE && c->N >= PM_BLOCKED_MIN_N) {
+    probe({MFQ_PATH_LAUNCHES, MFQ_TILE_AUTO, MFQ_ORDER_XCD, MFQ_PM_BLOCKED});
+    probe({MFQ_PATH_LAUNCHES, MFQ_TILE_AUTO, MFQ_ORDER_XCD, MFQ_PM_WORKGROUP});
+    pm = best.pm;
   }
-  out->n_candidates = (int32_t)cands.size();
+  for (int tile : {MFQ_TILE_AUTO, MFQ_TILE_SMALL, MFQ_TILE_LARGE})
+    for (int order : {MFQ_ORDER_XCD, MFQ_ORDER_LINEAR}) {
+      const Cand k{MFQ_PATH_LAUNCHES, tile, order, pm};
+      bool seen = false;
+      for (int i = 0; i < n; ++i)
+        seen = seen || (out->cand_path[i] == k.path && out->cand_tile[i] == k.tile &&
+                        out->cand_order[i] == k.order && out->cand_pm[i] == k.pm);
+      if (!seen) probe(k);
+    }
+  const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
+  if (fused_fits(c->L, c->N, c->lat.Lx, Ly) && !(protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4))
+    probe({MFQ_PATH_FUSED, MFQ_TILE_AUTO, MFQ_ORDER_XCD, pm});
+  out->n_candidates = n;
   const std::string probe_err = c->err;
   if (he == hipSuccess) he = restore();
   if (he == hipSuccess) he = copy_events(false);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
   (void)hipFree(save);
   drop_graph(c);
-  if (he != hipSuccess) {
+  auto keep_previous = [&]() {
     c->run_path = path0;
     c->tile_mode = tile0;
+    c->tile_order = order0;
+    c->pm_path = pm0;
+  };
+  if (he != hipSuccess) {
+    keep_previous();
     return hip_fail(c, he, "autotune");
   }
-  if (st != MFQ_OK || best < 0) {
-    c->run_path = path0;
-    c->tile_mode = tile0;
+  if (st != MFQ_OK || !have_best) {
+    keep_previous();
     return fail(c, st ? st : MFQ_EDEVICE, "autotune probe failed: " + probe_err);
   }
-  c->run_path = cands[best].path;
-  c->tile_mode = cands[best].tile;
-  out->path = c->run_path;
-  out->tile = c->tile_mode;
+  c->run_path = best.path;
+  c->tile_mode = best.tile;
+  c->tile_order = best.order;
+  c->pm_path = best.pm;
+  out->path = best.path;
+  out->tile = best.tile;
+  out->order = best.order;
+  out->pm_path = best.pm;
   out->ms_per_step = best_ms / probe_steps;
   return MFQ_OK;
 }

@@ -44,6 +44,9 @@ struct GemmDesc {
   // and its operands sit at X + (b / batch2) sX + (b % batch2) sX2 (batch2 <= 1: X + b sX).
   int batch2;
   long sA2, sB2, sD2, sCin2;
+  // Workgroup -> tile order, set by zgemm from the calling thread's choice
+  // (set_gemm_tile_order): 0 XCD-grouped, 1 plain linear.
+  int linear_order;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);
@@ -54,6 +57,12 @@ hipError_t zgemm(const GemmDesc &g, hipStream_t s);
 enum { GEMM_TILE_AUTO = 0, GEMM_TILE_SMALL = 1, GEMM_TILE_LARGE = 2 };
 void set_gemm_tile_mode(int mode);
 int gemm_tile_mode();
+// Order in which the workgroups of a GEMM walk its tiles, for the calling thread:
+// XCD (all tiles of one batch entry, or one column panel, on one XCD and its L2) or
+// LINEAR (tile index = workgroup index).  Results are bitwise the same either way.
+enum { GEMM_ORDER_XCD = 0, GEMM_ORDER_LINEAR = 1 };
+void set_gemm_tile_order(int order);
+int gemm_tile_order();
 // Doubles of partial results that a reduction-epilogue product g writes (0 if none).
 size_t zgemm_partials(const GemmDesc &g);
 // From the diagonal partials of the upper product C = U U^+ (M = N = L): for every batch entry

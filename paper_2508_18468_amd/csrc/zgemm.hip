@@ -50,7 +50,8 @@ struct TileMap {
   bool linear;                            // fewer groups than XCDs: plain linear order
 };
 
-__host__ __device__ inline TileMap make_map(int M, int N, int batch, int MT, int NT, int tri) {
+__host__ __device__ inline TileMap make_map(int M, int N, int batch, int MT, int NT, int tri,
+                                            int linear_order) {
   TileMap t;
   t.tilesM = (M + MT - 1) / MT;
   t.tilesN = (N + NT - 1) / NT;
@@ -59,11 +60,7 @@ __host__ __device__ inline TileMap make_map(int M, int N, int batch, int MT, int
   t.groups = t.by_panel ? batch * t.tilesN : batch;
   t.per_group = t.by_panel ? t.tilesM
               : t.upper ? t.tilesM * (t.tilesM + 1) / 2 : t.tilesM * t.tilesN;
-#ifdef MFQ_LINEAR_TILE_MAP
-  t.linear = true;
-#else
-  t.linear = t.groups < NXCD;
-#endif
+  t.linear = linear_order != 0 || t.groups < NXCD;
   return t;
 }
 
@@ -178,7 +175,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   constexpr int IM = MT / WM / 16, JN = NT / WN / 16;  // 16x16 blocks per wave
   constexpr int LA = MT * KT / NTHR, LB = NT * KT / NTHR;
   if (g.skip_if_le && *g.skip_if_le <= g.skip_thr) return;
-  const TileMap map = make_map(g.M, g.N, g.batch, MT, NT, g.tri);
+  const TileMap map = make_map(g.M, g.N, g.batch, MT, NT, g.tri, g.linear_order);
   const int id = blockIdx.x;
   const int k_on_xcd = map.linear ? id : id / NXCD;
   const int grp = map.linear ? id / map.per_group : id % NXCD + NXCD * (k_on_xcd / map.per_group);
@@ -418,12 +415,14 @@ __global__ __launch_bounds__(256) void propagator_zgemm_kernel_t64(GemmDesc g) {
   zgemm_body<OP_N, OP_N, 64, 64, kchunk<64>(), false, EDGE>(g);
 }
 
-// Tile choice of the calling thread (see set_gemm_tile_mode).
+// Tile choice and tile order of the calling thread (see set_gemm_tile_mode and
+// set_gemm_tile_order).
 thread_local int tl_tile_mode = GEMM_TILE_AUTO;
+thread_local int tl_tile_order = GEMM_ORDER_XCD;
 
 template <int MT, int NT>
 unsigned grid_size(const GemmDesc &g) {
-  const TileMap t = make_map(g.M, g.N, g.batch, MT, NT, g.tri);
+  const TileMap t = make_map(g.M, g.N, g.batch, MT, NT, g.tri, g.linear_order);
   if (t.linear) return (unsigned)((long)t.groups * t.per_group);
   const long groups_per_xcd = (t.groups + NXCD - 1) / NXCD;
   return (unsigned)(groups_per_xcd * NXCD * t.per_group);
@@ -491,9 +490,13 @@ hipError_t launch(const GemmDesc &g, hipStream_t s) {
 
 void set_gemm_tile_mode(int mode) { tl_tile_mode = mode; }
 int gemm_tile_mode() { return tl_tile_mode; }
+void set_gemm_tile_order(int order) { tl_tile_order = order; }
+int gemm_tile_order() { return tl_tile_order; }
 
-hipError_t zgemm_propagator(const GemmDesc &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+hipError_t zgemm_propagator(const GemmDesc &g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return hipSuccess;
+  GemmDesc g = g0;
+  g.linear_order = tl_tile_order;
   if (tl_tile_mode == GEMM_TILE_SMALL) {
     const dim3 grid(grid_size<64, 64>(g));
     if (needs_edge<64, 64>(g)) hipLaunchKernelGGL(propagator_zgemm_kernel_t64<true>, grid, dim3(256), 0, s, g);
@@ -517,8 +520,10 @@ int pick_tile(const GemmDesc &g) {
   return 64;
 }
 
-hipError_t zgemm(const GemmDesc &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+hipError_t zgemm(const GemmDesc &g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return hipSuccess;
+  GemmDesc g = g0;
+  g.linear_order = tl_tile_order;
   return pick_tile(g) == 128 ? launch<128, 128>(g, s) : launch<64, 64>(g, s);
 }
 

@@ -48,10 +48,18 @@ class RunArgs(ctypes.Structure):
                 ("n_obs", ctypes.c_int32)]
 
 
+TUNE_MAX_CANDIDATES = 16
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("tile", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
-                ("n_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("candidate_ms", ctypes.c_double * 8)]
+                ("n_candidates", ctypes.c_int32), ("order", ctypes.c_int32), ("pm_path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("candidate_ms", ctypes.c_double * TUNE_MAX_CANDIDATES),
+                ("cand_path", ctypes.c_int32 * TUNE_MAX_CANDIDATES),
+                ("cand_tile", ctypes.c_int32 * TUNE_MAX_CANDIDATES),
+                ("cand_order", ctypes.c_int32 * TUNE_MAX_CANDIDATES),
+                ("cand_pm", ctypes.c_int32 * TUNE_MAX_CANDIDATES)]
 
 
 class EngineStats(ctypes.Structure):
@@ -105,6 +113,7 @@ _SIGS = {
     "mfq_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p]),
     "mfq_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "mfq_set_tile_order": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "mfq_density_correlation": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_density_correlation_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "mfq_set_propagator": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
@@ -350,8 +359,7 @@ def mfq_reset_trajectory(ctx, slot, uid):
 
 
 TILE_AUTO, TILE_SMALL, TILE_LARGE = 0, 1, 2
-TUNE_CANDIDATES = [("launches", TILE_AUTO), ("launches", TILE_SMALL), ("launches", TILE_LARGE),
-                   ("fused", TILE_AUTO)]
+ORDER_XCD, ORDER_LINEAR = 0, 1
 
 
 def mfq_autotune(ctx, protocol, gamma, dt, seed, probe_steps):
@@ -359,12 +367,20 @@ def mfq_autotune(ctx, protocol, gamma, dt, seed, probe_steps):
     t = Tuning()
     _check(ctx, lib().mfq_autotune(ctx, int(protocol), _ptr(g), float(dt), int(seed), int(probe_steps),
                                    ctypes.byref(t)))
-    return {"path": t.path, "tile": t.tile, "ms_per_step": t.ms_per_step,
-            "candidate_ms": [t.candidate_ms[i] for i in range(t.n_candidates)]}
+    n = t.n_candidates
+    return {"path": t.path, "tile": t.tile, "order": t.order, "pm_path": t.pm_path,
+            "ms_per_step": t.ms_per_step,
+            "candidate_ms": [t.candidate_ms[i] for i in range(n)],
+            "candidates": [{"path": t.cand_path[i], "tile": t.cand_tile[i], "order": t.cand_order[i],
+                            "pm_path": t.cand_pm[i]} for i in range(n)]}
 
 
 def mfq_set_tuning(ctx, path, tile):
     _check(ctx, lib().mfq_set_tuning(ctx, int(path), int(tile)))
+
+
+def mfq_set_tile_order(ctx, order):
+    _check(ctx, lib().mfq_set_tile_order(ctx, int(order)))
 
 
 PROP_DENSE, PROP_FACTORED = 0, 1
@@ -601,20 +617,24 @@ class Trajectories:
 
     def autotune(self, protocol, gamma, dt, seed, probe_steps=4, cache=None):
         """Tune the execution form (mfq_autotune) or reuse a choice cached in the JSON file
-        `cache` under a key of device, lattice, N, batch, protocol and precision."""
+        `cache` under a key of device architecture, lattice, N, batch, protocol and precision."""
         import json
         import os
         import torch
-        key = "|".join(str(x) for x in (torch.cuda.get_device_name(self.device), self.lat.dim,
-                                         self.lat.Lx, self.lat.Ly, self.N, self.n_traj, protocol,
-                                         self.precision))
+        props = torch.cuda.get_device_properties(self.device)
+        arch = getattr(props, "gcnArchName", props.name)
+        key = "|".join(str(x) for x in (arch, self.lat.dim, self.lat.Lx, self.lat.Ly, self.N,
+                                         self.n_traj, protocol, self.precision))
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
         if key in table:
-            mfq_set_tuning(self.ctx, table[key]["path"], table[key]["tile"])
-            return dict(table[key], cached=True)
+            t = table[key]
+            mfq_set_tuning(self.ctx, t["path"], t["tile"])
+            mfq_set_tile_order(self.ctx, t["order"])
+            mfq_set_pm_path(self.ctx, t["pm_path"])
+            return dict(t, cached=True)
         g = np.broadcast_to(np.asarray(gamma, dtype=np.float64), (self.n_traj,))
         res = mfq_autotune(self.ctx, protocol, g, dt, seed, probe_steps)
         if cache:
@@ -623,6 +643,10 @@ class Trajectories:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1)
         return dict(res, cached=False)
+
+    def set_tile_order(self, order):
+        """GEMM workgroup -> tile order: ORDER_XCD (default) or ORDER_LINEAR (mfq_set_tile_order)."""
+        mfq_set_tile_order(self.ctx, order)
 
     def use_graphs(self, enable=True):
         mfq_use_graphs(self.ctx, enable)
