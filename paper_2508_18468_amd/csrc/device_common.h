@@ -268,15 +268,24 @@ __device__ inline void tridiag_body(cplx *A, int ld, int n, cplx *v, cplx *p, do
     if (s_skip) continue;
     const double tau = s_tau;
     cplx *A22 = A + (k + 1) + (long)(k + 1) * ld;
-    // p = tau A22 v
-    for (int i = tid; i < m; i += 256) {
+    // p = tau A22 v: tpr adjacent lanes per row (as many as 256 threads allow, up to 8),
+    // each summing every tpr-th column, then a shuffle tree within the lanes of the row
+    const int tpr = m <= 32 ? 8 : m <= 64 ? 4 : m <= 128 ? 2 : 1;
+    const int sub = tid % tpr;
+    for (int i0 = 0; i0 < m; i0 += 256 / tpr) {
+      const int i = i0 + tid / tpr;
       double ar = 0.0, ai = 0.0;
-      for (int j = 0; j < m; ++j) {
-        const cplx a = A22[i + (long)j * ld], vj = v[j];
-        ar += a.re * vj.re - a.im * vj.im;
-        ai += a.re * vj.im + a.im * vj.re;
+      if (i < m)
+        for (int j = sub; j < m; j += tpr) {
+          const cplx a = A22[i + (long)j * ld], vj = v[j];
+          ar += a.re * vj.re - a.im * vj.im;
+          ai += a.re * vj.im + a.im * vj.re;
+        }
+      for (int o = tpr / 2; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o, 64);
+        ai += __shfl_xor(ai, o, 64);
       }
-      p[i] = cplx{tau * ar, tau * ai};
+      if (i < m && sub == 0) p[i] = cplx{tau * ar, tau * ai};
     }
     __syncthreads();
     // K = (tau/2) v^+ p
@@ -297,15 +306,26 @@ __device__ inline void tridiag_body(cplx *A, int ld, int n, cplx *v, cplx *p, do
       p[i] = q;
     }
     __syncthreads();
-    // A22 -= v w^+ + w v^+
-    for (int i = tid; i < m; i += 256) {
-      const cplx vi = v[i], wi = p[i];
-      for (int j = 0; j < m; ++j) {
-        const cplx vj = v[j], wj = p[j];
+    // A22 -= v w^+ + w v^+ (entry by entry over the workgroup when m^2 is small)
+    if (m <= 128) {
+      for (int idx = tid; idx < m * m; idx += 256) {
+        const int i = idx % m, j = idx / m;
+        const cplx vi = v[i], wi = p[i], vj = v[j], wj = p[j];
         cplx a = A22[i + (long)j * ld];
         a.re -= (vi.re * wj.re + vi.im * wj.im) + (wi.re * vj.re + wi.im * vj.im);
         a.im -= (vi.im * wj.re - vi.re * wj.im) + (wi.im * vj.re - wi.re * vj.im);
         A22[i + (long)j * ld] = a;
+      }
+    } else {
+      for (int i = tid; i < m; i += 256) {
+        const cplx vi = v[i], wi = p[i];
+        for (int j = 0; j < m; ++j) {
+          const cplx vj = v[j], wj = p[j];
+          cplx a = A22[i + (long)j * ld];
+          a.re -= (vi.re * wj.re + vi.im * wj.im) + (wi.re * vj.re + wi.im * vj.im);
+          a.im -= (vi.im * wj.re - vi.re * wj.im) + (wi.im * vj.re - wi.re * vj.im);
+          A22[i + (long)j * ld] = a;
+        }
       }
     }
     __syncthreads();

@@ -6,12 +6,13 @@
 // step are each far too small to fill the GPU and the step is dominated by
 // launch and synchronisation latency.  Here every phase of Appendix A's step
 // runs back to back inside the workgroup:
-//   U' = P U (a dense product over all L^2 entries of P, whose entries are
-//   generated from the ring's circulant row -- or, on the torus, the two
-//   rows of P = P_y (x) P_x -- held in LDS),
+//   U' = P U (a dense product over all L^2 entries of P on the matrix cores,
+//   the entries generated from the ring's circulant row -- or, on the torus,
+//   the two rows of P = P_y (x) P_x -- held in LDS),
 //   Born probabilities + homodyne factor (Eq. (A4)) or projective
-//   measurements (Eq. (A1), Eq. (A2)), two Cholesky-QR passes (Gram, Cholesky
-//   and triangular inverse in LDS, U R^{-1}), and, when the absolute step is a
+//   measurements (Eq. (A1), Eq. (A2)), two Cholesky-QR passes (Gram on the
+//   matrix cores, Cholesky and triangular solve U R^{-1} in LDS; the second
+//   pass keeps a state its Gram certifies), and, when the absolute step is a
 //   multiple of obs_every, S_A of one region (Gram of the region rows,
 //   Householder tridiagonalisation, bisection, entropy sum; Sec. II).
 // Random numbers are the same Philox draws as the per-phase kernels, so the
@@ -54,99 +55,139 @@ __host__ __device__ inline FusedLayout fused_layout(int L, int N, int Lx, int Ly
   return f;
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// C = A B for small LDS-resident operands on the matrix cores (v_mfma_f64_16x16x4f64, four
+// real products per complex one): the M x Nc result in 16 x 16 blocks, spread over the
+// workgroup's four waves; a(m, k) and b(k, n) give the operands (zero outside M x K and
+// K x Nc) and put(m, n, v) receives each entry of C inside M x Nc.  upper: only the blocks
+// that meet the upper triangle (m <= n) are formed.  Operand lane layout: A lane l holds
+// A[l % 16][l / 16], B lane l holds B[l / 16][l % 16]; result register r of lane l is
+// C[l / 16 + 4 r][l % 16].
+template <class FA, class FB, class FPut>
+__device__ __forceinline__ void mfma_product(int M, int Nc, int K, FA a, FB b, FPut put, bool upper) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int bm_n = (M + 15) / 16, bn_n = (Nc + 15) / 16;
+  for (int blk = wave; blk < bm_n * bn_n; blk += 4) {
+    const int bm = blk % bm_n, bn = blk / bm_n;
+    if (upper && bm > bn) continue;
+    const int m = bm * 16 + (lane & 15), n = bn * 16 + (lane & 15);
+    f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const cplx av = (m < M && k < K) ? a(m, k) : cplx{0.0, 0.0};
+      const cplx bv = (k < K && n < Nc) ? b(k, n) : cplx{0.0, 0.0};
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.re, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.im, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.im, bv.im, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.im, bv.re, ci, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = bm * 16 + (lane >> 4) + 4 * r, col = bn * 16 + (lane & 15);
+      if (row < M && col < Nc) put(row, col, cplx{cr[r], ci[r]});
+    }
+  }
+}
+
 // One Cholesky-QR pass in LDS, in place: X <- X R^{-1}, R^+ R = X^+ X (upper
 // R).  X has leading dimension lu (>= L); G (the Gram, then R) has leading
-// dimension lg (>= N); rdiag receives the diagonal of R.  Gram with four
-// independent partial sums per entry, right-looking Cholesky in one wave, then
-// the triangular solve Y R = X (Y overwrites X) one row per thread.  A non-positive or
+// dimension lg (>= N); rdiag receives the diagonal of R; rowk (N entries) is
+// scratch.  Gram on the matrix cores (upper blocks), right-looking Cholesky, then
+// the triangular solve Y R = X (Y overwrites X) by four lanes per row.  A non-positive or
 // non-finite pivot sets *bad to its column + 1 and *bad_pivot to its value (first one only).
 // With certify, X is kept as it is when its Gram is within CHOL_KEEP_MAX of the identity
 // entrywise (|Re| + |Im| of G - I), as the second pass of the per-phase path does.
-__device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, int L, int N, int lu, int lg, int *bad,
-                           double *bad_pivot, bool certify) {
+__device__ void cholqr_lds(cplx *X, cplx *G, double *rdiag, cplx *rowk, int L, int N, int lu, int lg,
+                           int *bad, double *bad_pivot, bool certify) {
   const int tid = threadIdx.x;
   // largest deviation as the bit pattern of a non-negative double (NaN orders above all)
   __shared__ unsigned long long dev_bits;
   if (tid == 0) dev_bits = 0ull;
   __syncthreads();
   double dmax = 0.0;
-  for (int idx = tid; idx < N * N; idx += 256) {
-    const int a = idx % N, c = idx / N;
-    if (a > c) continue;
-    const cplx *xa = X + a * lu, *xc = X + c * lu;
-    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
-    int i = 0;
-    for (; i + 4 <= L; i += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const cplx p = xa[i + u], q = xc[i + u];
-        sr[u] += p.re * q.re + p.im * q.im;
-        si[u] += p.re * q.im - p.im * q.re;
-      }
-    }
-    for (; i < L; ++i) {
-      const cplx p = xa[i], q = xc[i];
-      sr[0] += p.re * q.re + p.im * q.im;
-      si[0] += p.re * q.im - p.im * q.re;
-    }
-    const cplx gac{(sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3])};
-    G[a + c * lg] = gac;
-    const double dv = fabs(a == c ? gac.re - 1.0 : gac.re) + fabs(gac.im);
-    dmax = (dv != dv || dmax != dmax) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(dmax, dv);
-  }
+  mfma_product(
+      N, N, L, [&](int m, int k) { const cplx v = X[k + m * lu]; return cplx{v.re, -v.im}; },
+      [&](int k, int n) { return X[k + n * lu]; },
+      [&](int r, int c, cplx g) {
+        if (r > c) return;
+        G[r + c * lg] = g;
+        const double dv = fabs(r == c ? g.re - 1.0 : g.re) + fabs(g.im);
+        dmax = (dv != dv || dmax != dmax) ? __longlong_as_double(0x7ff8000000000000ll) : fmax(dmax, dv);
+      },
+      true);
   if (certify) atomicMax(&dev_bits, (unsigned long long)__double_as_longlong(dmax));
   __syncthreads();  // the Gram is written by every wave
   if (certify && __longlong_as_double((long long)dev_bits) <= CHOL_KEEP_MAX) return;
-  // Cholesky by wave 0 alone: lanes of one wave run in lockstep, so the
-  // column steps need only wave-level ordering, not workgroup barriers
-  if (tid < 64) {
-    const int lane = tid;
-    for (int k = 0; k < N; ++k) {
-      double d = G[k + k * lg].re;
-      const bool ok = d > 0.0 && isfinite(d);
-      if (lane == 0 && !ok && *bad == 0) {
-        *bad = k + 1;
-        *bad_pivot = d;
-      }
-      if (!ok) d = 1.0;
-      const double rkk = sqrt(d);
-      if (lane == 0) rdiag[k] = rkk;
-      for (int j = k + 1 + lane; j < N; j += 64) {
-        G[k + j * lg].re /= rkk;
-        G[k + j * lg].im /= rkk;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int m = N - k - 1;
-      for (int idx = lane; idx < m * m; idx += 64) {
-        const int i = k + 1 + idx % m, j = k + 1 + idx / m;
-        if (i > j) continue;
-        const cplx rki = G[k + i * lg], rkj = G[k + j * lg];
-        G[i + j * lg].re -= rki.re * rkj.re + rki.im * rkj.im;
-        G[i + j * lg].im -= rki.re * rkj.im - rki.im * rkj.re;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Right-looking Cholesky over the whole workgroup: at step k the scaled row k of R is
+  // also copied to rowk, whose entries the trailing update of that step reads (a separate
+  // buffer, so that those loads do not wait for the update's stores).
+  for (int k = 0; k < N; ++k) {
+    double d = G[k + k * lg].re;
+    const bool ok = d > 0.0 && isfinite(d);
+    if (tid == 0 && !ok && *bad == 0) {
+      *bad = k + 1;
+      *bad_pivot = d;
     }
+    if (!ok) d = 1.0;
+    const double rkk = sqrt(d);
+    if (tid == 0) rdiag[k] = rkk;
+    for (int j = k + 1 + tid; j < N; j += 256) {
+      cplx r = G[k + j * lg];
+      r.re /= rkk;
+      r.im /= rkk;
+      G[k + j * lg] = r;
+      rowk[j] = r;
+    }
+    __syncthreads();
+    const int m = N - k - 1;
+    const cplx *__restrict__ rk = rowk + (k + 1);
+    cplx *__restrict__ g = G + (k + 1) + (long)(k + 1) * lg;
+    for (int idx = tid; idx < m * m; idx += 256) {
+      const int i = idx % m, j = idx / m;
+      if (i > j) continue;
+      const cplx rki = rk[i], rkj = rk[j];
+      cplx a = g[i + j * lg];
+      a.re -= rki.re * rkj.re + rki.im * rkj.im;
+      a.im -= rki.re * rkj.im - rki.im * rkj.re;
+      g[i + j * lg] = a;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // Y R = X row by row: each row is an independent forward substitution, so a
-  // thread owns a row and no barrier is needed inside
-  for (int i = tid; i < L; i += 256) {
-    for (int j = 0; j < N; ++j) {
-      const double inv = 1.0 / rdiag[j];
-      cplx y = X[i + j * lu];
-      y.re *= inv;
-      y.im *= inv;
-      X[i + j * lu] = y;
-      for (int c = j + 1; c < N; ++c) {
-        const cplx r = G[j + c * lg];
-        cplx x = X[i + c * lu];
-        x.re -= y.re * r.re - y.im * r.im;
-        x.im -= y.re * r.im + y.im * r.re;
-        X[i + c * lu] = x;
+  // Y R = X: each row is an independent forward substitution, run by four lanes
+  // of one wave (64 rows per pass), which split the updates of the later
+  // columns; only wave-level ordering is needed between the column steps.
+  {
+    const int q = tid & 3;
+    for (int i0 = 0; i0 < L; i0 += 64) {
+      const int i = i0 + (tid >> 2);
+      const bool row = i < L;
+      for (int j = 0; j < N; ++j) {
+        const double inv = 1.0 / rdiag[j];
+        cplx y{0.0, 0.0};
+        if (row) {
+          y = X[i + j * lu];
+          y.re *= inv;
+          y.im *= inv;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (row) {
+          if (q == 0) X[i + j * lu] = y;
+          const cplx *__restrict__ rj = G + j;
+          cplx *__restrict__ xi = X + i;
+          for (int c = j + 1 + q; c < N; c += 4) {
+            const cplx r = rj[c * lg];
+            cplx x = xi[c * lu];
+            x.re -= y.re * r.re - y.im * r.im;
+            x.im -= y.re * r.im + y.im * r.re;
+            xi[c * lu] = x;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
     }
   }
@@ -191,40 +232,19 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
   for (int s = 1; s <= a.n_steps; ++s) {
     const uint64_t n = (uint64_t)(a.step0 + s - base);  // this trajectory's own step index
     const int64_t n_ctx = a.step0 + s;                   // the context's step (observation schedule)
-    // propagate: Ub = P Ua, with the dense P_ik = gx[(xi - xk) mod Lx] gy[(yi - yk) mod Ly]
-    // generated from the generating rows held in LDS (all L^2 terms are summed)
-    for (int idx = tid; idx < L * N; idx += 256) {
-      const int i = idx % L, j = idx / L;
-      const int xi = i % Lx, yi = i / Lx;
-      const cplx *uj = Ua + j * lu;
-      double sr = 0.0, si = 0.0;
-      for (int yk = 0; yk < Ly; ++yk) {
-        const int dy = yi - yk;
-        const cplx py = gy[dy < 0 ? dy + Ly : dy];
-        double tr4[4] = {0.0, 0.0, 0.0, 0.0}, ti4[4] = {0.0, 0.0, 0.0, 0.0};
-        int xk = 0;
-        for (; xk + 4 <= Lx; xk += 4) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int dx = xi - (xk + q);
-            const cplx px = gx[dx < 0 ? dx + Lx : dx], u = uj[xk + q + yk * Lx];
-            tr4[q] += px.re * u.re - px.im * u.im;
-            ti4[q] += px.re * u.im + px.im * u.re;
-          }
-        }
-        for (; xk < Lx; ++xk) {
-          const int dx = xi - xk;
-          const cplx px = gx[dx < 0 ? dx + Lx : dx], u = uj[xk + yk * Lx];
-          tr4[0] += px.re * u.re - px.im * u.im;
-          ti4[0] += px.re * u.im + px.im * u.re;
-        }
-        const double tr = (tr4[0] + tr4[1]) + (tr4[2] + tr4[3]);
-        const double ti = (ti4[0] + ti4[1]) + (ti4[2] + ti4[3]);
-        sr += py.re * tr - py.im * ti;
-        si += py.re * ti + py.im * tr;
-      }
-      Ub[i + j * lu] = cplx{sr, si};
-    }
+    // propagate: Ub = P Ua on the matrix cores, with the dense P_ik = gx[(xi - xk) mod Lx]
+    // gy[(yi - yk) mod Ly] generated from the generating rows held in LDS (all L^2 terms)
+    mfma_product(
+        L, N, L,
+        [&](int i, int k) {
+          int dx = i % Lx - k % Lx, dy = i / Lx - k / Lx;
+          dx += dx < 0 ? Lx : 0;
+          dy += dy < 0 ? Ly : 0;
+          const cplx px = gx[dx], py = gy[dy];
+          return cplx{px.re * py.re - px.im * py.im, px.re * py.im + px.im * py.re};
+        },
+        [&](int k, int j) { return Ua[k + j * lu]; }, [&](int i, int j, cplx v) { Ub[i + j * lu] = v; },
+        false);
     __syncthreads();
     if (a.protocol == 1) {
       // Born probability and homodyne factor, one row per thread
@@ -248,8 +268,8 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
                                   lu);
       __syncthreads();
     }
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot, false);
-    cholqr_lds(Ub, G, lam, L, N, lu, lg, &bad, &bad_pivot, true);
+    cholqr_lds(Ub, G, lam, vv, L, N, lu, lg, &bad, &bad_pivot, false);
+    cholqr_lds(Ub, G, lam, vv, L, N, lu, lg, &bad, &bad_pivot, true);
     // state now in Ub: swap so that it is in Ua for the next step
     cplx *t = Ua;
     Ua = Ub;
