@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
+#include <system_error>
 #include <thread>
 
 #include "../../include/mfq.h"
@@ -220,16 +221,22 @@ void worker_loop(mfq_engine *e) {
     {
       std::vector<std::thread> th;
       std::vector<double> t0(blocking.size());
+      auto advance = [e, &blocking, &t0](size_t i) {
+        Pending &b = blocking[i];
+        (void)hipSetDevice(e->device);
+        t0[i] = e->now();
+        (void)hipEventRecord(b.r.e0, b.r.s);
+        b.st = mfq_step(b.r.c, b.key.protocol, b.gam.data(), b.key.dt, b.key.seed, b.k);
+        (void)hipEventRecord(b.r.e1, b.r.s);
+      };
       th.reserve(blocking.size());
-      for (size_t i = 0; i < blocking.size(); ++i)
-        th.emplace_back([e, &blocking, &t0, i] {
-          Pending &b = blocking[i];
-          (void)hipSetDevice(e->device);
-          t0[i] = e->now();
-          (void)hipEventRecord(b.r.e0, b.r.s);
-          b.st = mfq_step(b.r.c, b.key.protocol, b.gam.data(), b.key.dt, b.key.seed, b.k);
-          (void)hipEventRecord(b.r.e1, b.r.s);
-        });
+      for (size_t i = 0; i < blocking.size(); ++i) {
+        try {
+          th.emplace_back(advance, i);
+        } catch (const std::system_error &) {  // no thread available: advance it here
+          advance(i);
+        }
+      }
       for (std::thread &t : th) t.join();
       for (size_t i = 0; i < blocking.size(); ++i)
         runs.push_back({blocking[i].gid, blocking[i].k, blocking[i].r, t0[i], blocking[i].st, nullptr});
