@@ -704,6 +704,37 @@ __global__ __launch_bounds__(256) void entropy_kernel(EigWork w, int n) {
   if (threadIdx.x == 0) w.S[b] = s;
 }
 
+// The strictly lower triangle of each n x n Hermitian matrix from its upper triangle:
+// A[i][j] = conj(A[j][i]) for i > j (column-major, ld n).  Workgroups walk 32 x 32 blocks
+// of the lower triangle; the block's mirror image is staged through LDS so that both the
+// reads and the writes run along columns.
+__global__ __launch_bounds__(256) void hermitian_lower_kernel(cplx *A, int n) {
+  const int nb = (n + 31) / 32;
+  const int b = blockIdx.y;
+  cplx *Ab = A + (long)b * n * n;
+  __shared__ cplx t[32][33];
+  for (int blk = blockIdx.x; blk < nb * (nb + 1) / 2; blk += gridDim.x) {
+    int bj = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);  // block column of the upper triangle
+    while (bj * (bj + 1) / 2 > blk) --bj;
+    while ((bj + 1) * (bj + 2) / 2 <= blk) ++bj;
+    const int bi = blk - bj * (bj + 1) / 2;  // bi <= bj: upper block (bi, bj) mirrors to (bj, bi)
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {  // read upper block rows bi*32 + tx, columns bj*32 + r
+      const int i = bi * 32 + tx, j = bj * 32 + r;
+      if (i < n && j < n) t[r][tx] = Ab[i + (long)j * n];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {  // write lower block rows bj*32 + tx, columns bi*32 + r
+      const int i = bj * 32 + tx, j = bi * 32 + r;
+      if (i < n && j < n && i > j) {
+        const cplx v = t[tx][r];
+        Ab[i + (long)j * n] = cplx{v.re, -v.im};
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, int nreg, cplx *A,
@@ -712,6 +743,7 @@ hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, in
   g.alpha = cplx{1.0, 0.0};
   g.beta = cplx{0.0, 0.0};
   g.batch = B;
+  g.tri = TRI_UPPER;  // the upper triangle on the matrix cores, the lower one mirrored
   if (nreg <= N) {  // C_A = U_A U_A^+  (nreg x nreg)
     g.M = nreg; g.N = nreg; g.K = N;
     g.A = U; g.lda = L; g.sA = (long)L * N; g.opA = OP_N; g.idxA = region;
@@ -725,7 +757,12 @@ hipError_t region_gram(const cplx *U, int L, int N, int B, const int *region, in
     g.D = A; g.ldd = N; g.sD = (long)N * N;
     *n_out = N;
   }
-  return zgemm(g, s);
+  hipError_t e = zgemm(g, s);
+  if (e != hipSuccess) return e;
+  const int n = *n_out, nb = (n + 31) / 32;
+  const unsigned blocks = (unsigned)std::min(nb * (nb + 1) / 2, 1024);
+  hipLaunchKernelGGL(hermitian_lower_kernel, dim3(blocks, B), dim3(256), 0, s, A, n);
+  return hipGetLastError();
 }
 
 namespace {
