@@ -13,16 +13,19 @@
 //
 // Tiling: a workgroup owns an MT x NT complex tile of D; its wave64s form a
 // 2 x (NT/32) grid and each owns a block of 16 x 16 MFMA outputs with separate
-// real and imaginary accumulators.  Two shapes:
+// real and imaginary accumulators.  Shapes:
 //   64 x 64,   4 waves, 32 x 32 per wave   small or thin contractions;
 //   128 x 128, 8 waves, 64 x 32 per wave   the large ones: half the L2->CU
 //              bytes per flop of the small tile, 64 accumulator doubles per
-//              lane (more per wave would overflow the register file).
+//              lane (more per wave would overflow the register file);
+//   128 x 64,  4 waves, 64 x 32 per wave   the other large products with
+//              op(A) = A and a general result (the products with R^-1 among them).
 // K advances in chunks of 16; the next chunk is fetched into registers while the
 // current one feeds the matrix cores.  Products with op(A) = A (the propagator among
 // them) store it into their one LDS buffer between two barriers (66 KiB for
 // 128 x 128 tiles, whose ~208 VGPRs per lane allow one 512-thread workgroup per
-// compute unit); the Gram-shaped products (op(A) = A^+) and the reduction
+// compute unit; 128 x 64 tiles fit two); the Gram-shaped products
+// (op(A) = A^+) and the reduction
 // epilogues keep two buffers, store the next chunk after the first MFMA k-step of the
 // current one and pass one barrier per chunk.
 //
@@ -405,7 +408,9 @@ __global__ __launch_bounds__(nthreads<NT>()) void zgemm_kernel(GemmDesc g) {
 }
 
 // The propagator product U <- P U gets its own symbols so that profilers can
-// tell it apart from the other contractions of a step.
+// tell it apart from the other contractions of a step.  It keeps 128 x 128 tiles:
+// the 128 x 64 form of the other op(A) = A products ran it 0.5-1.6 % faster on the
+// 160x160 torus but fetched twice the HBM bytes (6.7 against 3.3 TB per launch).
 template <bool EDGE>
 __global__ __launch_bounds__(512) void propagator_zgemm_kernel(GemmDesc g) {
   zgemm_body<OP_N, OP_N, 128, 128, kchunk<128>(), false, EDGE>(g);
@@ -445,6 +450,39 @@ void launch_ops(const GemmDesc &g, dim3 grid, hipStream_t s) {
     hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
   else
     hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_C, MT, NT, GATHER, EDGE, FL>), grid, block, 0, s, g);
+}
+
+// Large products with op(A) = A and a general result (no triangular result, no epilogue;
+// the propagator has its own kernel) take 128 x 64 tiles held to two waves per SIMD: two
+// workgroups share a compute unit, and a triangular op(B) skips K in steps of 64 columns
+// instead of 128 (U R^-1 shaped products, 384 x (1024 x 256 x 256): 0.49 -> 0.56 of the FP64
+// peak against 4 L N^2; 3 x (25600 x 6400 x 6400): 0.77 -> 0.80).
+template <int OPB, bool GATHER, bool EDGE, int FL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void zgemm_wide_kernel(GemmDesc g) {
+  zgemm_body<OP_N, OPB, 128, 64, kchunk<128>(), GATHER, EDGE, FL>(g);
+}
+
+template <int OPB>
+void launch_wide_ops(const GemmDesc &g, hipStream_t s) {
+  const dim3 grid(grid_size<128, 64>(g)), block(256);
+  const bool edge = needs_edge<128, 64>(g);
+  if (g.idxA || g.idxB)
+    hipLaunchKernelGGL((zgemm_wide_kernel<OPB, true, true, 0>), grid, block, 0, s, g);
+  else if (g.aUpper || g.bUpper) {
+    if (edge) hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, true, FL_MASK>), grid, block, 0, s, g);
+    else hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, false, FL_MASK>), grid, block, 0, s, g);
+  } else if (edge) {
+    hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, true, 0>), grid, block, 0, s, g);
+  } else {
+    hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, false, 0>), grid, block, 0, s, g);
+  }
+}
+
+hipError_t launch_wide(const GemmDesc &g, hipStream_t s) {
+  if (g.opB == OP_N) launch_wide_ops<OP_N>(g, s);
+  else launch_wide_ops<OP_C>(g, s);
+  return hipGetLastError();
 }
 
 template <int MT, int NT>
@@ -524,7 +562,9 @@ hipError_t zgemm(const GemmDesc &g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return hipSuccess;
   GemmDesc g = g0;
   g.linear_order = tl_tile_order;
-  return pick_tile(g) == 128 ? launch<128, 128>(g, s) : launch<64, 64>(g, s);
+  if (pick_tile(g) != 128) return launch<64, 64>(g, s);
+  if (g.opA == OP_N && g.tri != TRI_UPPER && !g.part && !g.R1) return launch_wide(g, s);
+  return launch<128, 128>(g, s);
 }
 
 size_t zgemm_partials(const GemmDesc &g) {
