@@ -90,6 +90,122 @@ __device__ __forceinline__ void mfma_product(int M, int Nc, int K, FA a, FB b, F
   }
 }
 
+// Householder tridiagonalisation of the n x n Hermitian A (leading dimension ld, n <= 64)
+// by one wave, lane i owning row i: the same reflectors and updates as tridiag_body
+// (scaled reflector, p = tau A22 v, w = p - (tau/2)(v^+ p) v, A22 -= v w^+ + w v^+), with
+// wave reductions and wave-level ordering in place of workgroup barriers.  Output as
+// tridiag_body: d[0:n], e[0:n-1] = |off-diagonal|.  v, p: n scratch entries each.
+__device__ void tridiag_wave(cplx *A, int ld, int n, cplx *v, cplx *p, double *d, double *e) {
+  const int lane = threadIdx.x & 63;
+  auto wave_order = []() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    const cplx *x = A + (k + 1) + (long)k * ld;
+    const cplx xi = lane < m ? x[lane] : cplx{0.0, 0.0};
+    double s = cmax_abs(xi);
+    for (int o = 32; o > 0; o >>= 1) s = fmax(s, __shfl_xor(s, o, 64));
+    const double inv = s >= REFLECT_TINY ? 1.0 / s : 0.0;
+    const cplx a{xi.re * inv, xi.im * inv};
+    double tail2 = lane >= 1 && lane < m ? a.re * a.re + a.im * a.im : 0.0;
+    for (int o = 32; o > 0; o >>= 1) tail2 += __shfl_xor(tail2, o, 64);
+    const cplx x0 = x[0];
+    if (lane == 0) d[k] = A[k + (long)k * ld].re;
+    if (tail2 == 0.0) {  // nothing below x0 (or all below REFLECT_TINY): H = I
+      if (lane == 0) e[k] = hypot(x0.re, x0.im);
+      wave_order();
+      continue;
+    }
+    const Reflector h = make_reflector(cplx{x0.re * inv, x0.im * inv}, tail2, s);
+    const double tau = h.tau;
+    if (lane == 0) {
+      e[k] = h.norm;
+      v[0] = h.v0;
+    } else if (lane < m) {
+      v[lane] = a;
+    }
+    wave_order();
+    cplx *A22 = A + (k + 1) + (long)(k + 1) * ld;
+    cplx pi{0.0, 0.0};
+    if (lane < m) {
+      double ar = 0.0, ai = 0.0;
+      for (int j = 0; j < m; ++j) {
+        const cplx aij = A22[lane + (long)j * ld], vj = v[j];
+        ar += aij.re * vj.re - aij.im * vj.im;
+        ai += aij.re * vj.im + aij.im * vj.re;
+      }
+      pi = cplx{tau * ar, tau * ai};
+    }
+    const cplx vi = lane < m ? v[lane] : cplx{0.0, 0.0};
+    double pr = vi.re * pi.re + vi.im * pi.im, pim = vi.re * pi.im - vi.im * pi.re;
+    for (int o = 32; o > 0; o >>= 1) {
+      pr += __shfl_xor(pr, o, 64);
+      pim += __shfl_xor(pim, o, 64);
+    }
+    const double kr = 0.5 * tau * pr, ki = 0.5 * tau * pim;
+    const cplx wi{pi.re - (kr * vi.re - ki * vi.im), pi.im - (kr * vi.im + ki * vi.re)};
+    if (lane < m) p[lane] = wi;
+    wave_order();
+    if (lane < m) {
+      for (int j = 0; j < m; ++j) {
+        const cplx vj = v[j], wj = p[j];
+        cplx aij = A22[lane + (long)j * ld];
+        aij.re -= (vi.re * wj.re + vi.im * wj.im) + (wi.re * vj.re + wi.im * vj.im);
+        aij.im -= (vi.im * wj.re - vi.re * wj.im) + (wi.im * vj.re - wi.re * vj.im);
+        A22[lane + (long)j * ld] = aij;
+      }
+    }
+    wave_order();
+  }
+  if (lane == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(n - 2) + (long)(n - 2) * ld].re;
+      const cplx t = A[(n - 1) + (long)(n - 2) * ld];
+      e[n - 2] = hypot(t.re, t.im);
+    }
+    d[n - 1] = A[(n - 1) + (long)(n - 1) * ld].re;
+  }
+}
+
+// Eigenvalues lam[0:n] (ascending) of the tridiagonal (d, e) by multisection over the
+// workgroup: eight adjacent lanes per eigenvalue evaluate the Sturm count at eight interior
+// points of its bracket and keep the sub-interval where the count passes k (a ninth of the
+// bracket per round, against a half for bisection), on the same Gershgorin start, pivmin and
+// stopping width as bisect_eigenvalue.
+__device__ void multisect_eigenvalues(const double *d, const double *e, int n, double *lam) {
+  const int tid = threadIdx.x, lane = tid & 63, sub = tid & 7, base = lane & ~7;
+  double lo0 = d[0], hi0 = d[0], emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? e[i - 1] : 0.0) + (i + 1 < n ? e[i] : 0.0);
+    lo0 = fmin(lo0, d[i] - r);
+    hi0 = fmax(hi0, d[i] + r);
+    if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+  }
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  const double span = fmax(fabs(lo0), fabs(hi0));
+  lo0 -= 2.0 * 2.220446049250313e-16 * span + 2.0 * pivmin;
+  hi0 += 2.0 * 2.220446049250313e-16 * span + 2.0 * pivmin;
+  const double tol = 4.0 * 2.220446049250313e-16 * fmax(1.0, span);
+  for (int k0 = 0; k0 < n; k0 += 32) {  // 32 groups of eight lanes per round
+    const int k = k0 + (tid >> 3);
+    double lo = lo0, hi = hi0;
+    for (int it = 0; it < 40 && k < n && hi - lo > tol; ++it) {
+      const double x = lo + (hi - lo) * ((double)(sub + 1) / 9.0);
+      const bool above = sturm_count(d, e, n, x, pivmin) > k;
+      const unsigned mask = (unsigned)(__ballot(above) >> base) & 0xffu;
+      const int first = mask ? __ffs(mask) - 1 : 8;  // first of the eight points above k
+      const double nhi = __shfl(x, base + (first < 8 ? first : 0), 64);
+      const double nlo = __shfl(x, base + (first > 0 ? first - 1 : 0), 64);
+      if (first < 8) hi = nhi;
+      if (first > 0) lo = nlo;
+    }
+    if (k < n && sub == 0) lam[k] = bracket_estimate(lo, hi);
+  }
+}
+
 // One Cholesky-QR pass in LDS, in place: X <- X R^{-1}, R^+ R = X^+ X (upper
 // R).  X has leading dimension lu (>= L); G (the Gram, then R) has leading
 // dimension lg (>= N); rdiag receives the diagonal of R; rowk (N entries) is
@@ -305,9 +421,13 @@ __device__ __forceinline__ void fused_body(const FusedArgs &a, int b, unsigned c
           }
         }
         __syncthreads();
-        tridiag_body(G, m, m, vv, R, dd, ee, red);
+        if (m <= 64) {  // one wave: no workgroup barriers inside the reduction
+          if (tid < 64) tridiag_wave(G, m, m, vv, R, dd, ee);
+        } else {
+          tridiag_body(G, m, m, vv, R, dd, ee, red);
+        }
         __syncthreads();
-        for (int k = tid; k < m; k += 256) lam[k] = bisect_eigenvalue(dd, ee, m, k);
+        multisect_eigenvalues(dd, ee, m, lam);
         __syncthreads();
         double part = 0.0;
         for (int k = tid; k < m; k += 256) part += binary_entropy(lam[k]);
