@@ -4,7 +4,8 @@
 // The one-stage blocked reduction (eig.hip) reads the trailing matrix once per reflector:
 // about 8 n^3 / 3 bytes per matrix, bound by HBM.  Here the matrix is first reduced to a band
 // of half-width TRD2_SB by block reflectors whose two-sided updates are matrix-core products
-// (about 8 n^3 flop; the trailing matrix is read three times per panel of TRD2_SB columns),
+// (about 16 n^3 / 3 flop; the lower triangle of the trailing matrix is read three times and
+// written once per panel of TRD2_SB columns),
 // then the band is reduced to tridiagonal form by bulge chasing, whose work is O(n^2 TRD2_SB):
 //
 //   stage 1, per panel of TRD2_SB columns starting at column j (rows below the band:
@@ -13,7 +14,9 @@
 //     of the previous launch in the same fixed order, so all of them form the same reflector),
 //     leaving R in the band and zeros below it; then with Q = I - V T V^+ (compact WY),
 //     A22 <- Q^+ A22 Q = A22 - V W^+ - W V^+,  W = X - (1/2) V (T^+ (V^+ X)),  X = A22 (V T),
-//     the deep products split over K into slices summed in a fixed order;
+//     the deep products split over K into slices summed in a fixed order.  Only the lower
+//     triangle of A22 is kept: X is formed as tril(A22) (V T) + (strictly lower part)^+ (V T),
+//     and the update writes the tiles on and below the diagonal;
 //   stage 2, sweep j (column j) and task t: a reflector of length <= TRD2_SB removes column j
 //     below the sub-diagonal (t = 0) or the first column of the bulge task t - 1 created
 //     (t >= 1), applied to the rows it mixes (left), to its diagonal block (two-sided) and to
@@ -602,32 +605,32 @@ GemmDesc gdesc() {
 
 int groups_for(int n) { return trd2_groups(n); }
 
-// K slices for a product with `tiles` output tiles per matrix and depth K: enough workgroups
-// to fill the chip, slices of at least 256.
-int kslices(long tiles, int K, int B) {
+// K slices for a product with `tiles` output tiles per matrix and depth K: at most `wgs`
+// workgroups in all, slices at least `depth` deep.
+int kslices(long tiles, int K, int B, long wgs, int depth) {
   int ks = 1;
-  while (ks < KS_MAX && tiles * B * ks * 2 <= 1024 && K / (2 * ks) >= 256) ks *= 2;
+  while (ks < KS_MAX && tiles * B * ks * 2 <= wgs && K / (2 * ks) >= depth) ks *= 2;
   return ks;
 }
 
-// g (depth K) split over K into ks slices: slice q (q < ks - 1) of depth kc = ceil(K / ks), the
-// last of the remaining depth, each into its own partial D + q sDq.  dA, dB: operand offsets per
-// unit of K.  The slices' partials are summed by p1_ksum_kernel.
+// Slices of depth K that ksplit forms when asked for ks: their depth kc (whole K chunks when
+// split), and their number (every slice non-empty).
+int slice_depth(int K, int ks) {
+  const int kc = (K + ks - 1) / ks;
+  return ks > 1 ? (kc + 15) / 16 * 16 : kc;
+}
+int slice_count(int K, int ks) { return (K + slice_depth(K, ks) - 1) / slice_depth(K, ks); }
+
+// g (depth K) split over K in one launch into slice_count(K, ks) slices: slice q covers K
+// indices [q kc, min((q + 1) kc, K)), kc = slice_depth(K, ks), its partial into D + q sDq.
+// dA, dB: operand offsets per unit of K.  The slices' partials are summed by p1_ksum_kernel.
 hipError_t ksplit(GemmDesc g, int B, int K, int ks, long dA, long dB, long sDq, hipStream_t s) {
-  const int kc = (K + ks - 1) / ks, rem = K - (ks - 1) * kc;
-  hipError_t e;
-  if (ks > 1) {
-    GemmDesc f = g;
-    f.K = kc; f.batch = B * (ks - 1); f.batch2 = ks - 1;
-    f.sA2 = kc * dA; f.sB2 = kc * dB; f.sD2 = sDq;
-    if ((e = zgemm(f, s)) != hipSuccess) return e;
-  }
-  GemmDesc l = g;
-  l.K = rem; l.batch = B; l.batch2 = 1;
-  l.A = g.A + (long)(ks - 1) * kc * dA;
-  l.B = g.B + (long)(ks - 1) * kc * dB;
-  l.D = g.D + (long)(ks - 1) * sDq;
-  return zgemm(l, s);
+  const int kc = slice_depth(K, ks);
+  ks = slice_count(K, ks);
+  g.K = kc; g.batch = B * ks; g.batch2 = ks;
+  g.sA2 = kc * dA; g.sB2 = kc * dB; g.sD2 = sDq;
+  g.kofs = 0; g.kofs2 = kc; g.kend_glob = K;
+  return zgemm(g, s);
 }
 
 }  // namespace
@@ -647,7 +650,7 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {  // S = V^+ V
-      const int ks = kslices(1, m, B);
+      const int ks = slice_count(m, kslices(1, m, B, 512, 64));
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;
       g.A = s0.X; g.lda = n; g.sA = ps; g.opA = OP_C;
@@ -668,21 +671,26 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
       g.D = s0.VT; g.ldd = n; g.sD = ps;
       if ((e = zgemm(g, s)) != hipSuccess) return e;
     }
-    {  // X = A22 (V T), into the W columns of X
-      int ks = kslices((m + 63) / 64, m, B);
-      while (ks > 1 && (long)ks * m * SB > trd2_kp_elems(n)) ks /= 2;
+    {  // X = A22 (V T) from the lower triangle of A22: tril(A22) (V T) + striu(A22^+) (V T),
+       // each split over K, all partials summed into the W columns of X
+      int ks = kslices((m + 63) / 64, m, B, 4096, 128);
+      while (ks > 1 && 2L * ks * m * SB > trd2_kp_elems(n)) ks /= 2;
+      ks = slice_count(m, ks);
       GemmDesc g = gdesc();
       g.M = m; g.N = SB; g.batch = B;
-      g.A = A22; g.lda = n; g.sA = nn; g.opA = OP_N;
+      g.A = A22; g.lda = n; g.sA = nn; g.opA = OP_N; g.aLower = 1;
       g.B = s0.VT; g.ldb = n; g.sB = ps; g.opB = OP_N;
       g.D = s0.KP; g.ldd = m; g.sD = ps;
       if ((e = ksplit(g, B, m, ks, n, 1, (long)m * SB, s)) != hipSuccess) return e;
+      g.opA = OP_C; g.aLower = 0; g.aUpper = 2;
+      g.D = s0.KP + (long)ks * m * SB;
+      if ((e = ksplit(g, B, m, ks, 1, 1, (long)m * SB, s)) != hipSuccess) return e;
       hipLaunchKernelGGL(p1_ksum_kernel, dim3((unsigned)(((long)m * SB + 255) / 256), B), dim3(256), 0, s, w, n, g1,
-                         2, m, ks, (long)n);
+                         2, m, 2 * ks, (long)n);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {  // Z = V^+ X
-      const int ks = kslices(1, m, B);
+      const int ks = slice_count(m, kslices(1, m, B, 512, 64));
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;
       g.A = s0.X; g.lda = n; g.sA = ps; g.opA = OP_C;
@@ -715,15 +723,16 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
     hipLaunchKernelGGL(p1_swap_kernel, dim3((unsigned)(((long)m * 2 * SB + 255) / 256), B), dim3(256), 0, s, w, n,
                        g1, m);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    {  // A22 -= [V W] [W V]^+
+    {  // A22 -= [V W] [W V]^+, on and below the diagonal
       GemmDesc g = gdesc();
-      g.M = m; g.N = m; g.K = 2 * SB; g.batch = B;
+      g.M = m; g.N = m; g.K = 2 * SB; g.batch = B; g.tri = TRI_LOWER;
       g.A = s0.X; g.lda = n; g.sA = ps; g.opA = OP_N;
       g.B = s0.Y; g.ldb = n; g.sB = ps; g.opB = OP_C;
       g.Cin = A22; g.ldcin = n; g.sCin = nn;
       g.D = A22; g.ldd = n; g.sD = nn;
       g.alpha = cplx{-1.0, 0.0};
       g.beta = cplx{1.0, 0.0};
+      g.short_k_large = 1;
       if ((e = zgemm(g, s)) != hipSuccess) return e;
     }
   }

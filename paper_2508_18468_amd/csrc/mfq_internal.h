@@ -15,7 +15,7 @@ namespace mfq {
 // op = 0: as stored; op = 2: conjugate transpose.  Storage row indices of A and
 // B may be gathered through idxA / idxB (applied to the stored matrix rows).
 enum { OP_N = 0, OP_C = 2 };
-enum { TRI_NONE = 0, TRI_UPPER = 1 };
+enum { TRI_NONE = 0, TRI_UPPER = 1, TRI_LOWER = 2 };
 
 struct GemmDesc {
   int M, N, K, batch;
@@ -24,9 +24,16 @@ struct GemmDesc {
   const cplx *Cin; long ldcin, sCin;
   cplx *D; long ldd, sD;
   cplx alpha, beta;        // beta == 0 -> Cin is not read
-  int tri;                 // TRI_UPPER: only tiles touching the upper triangle of D
-  int aUpper;              // op(A) is upper triangular: A[m][k] taken as 0 for k < m (not read)
+  int tri;                 // TRI_UPPER / TRI_LOWER: only the tiles touching that triangle of D
+                           // (TRI_LOWER writes its entries on and below the diagonal only)
+  int aUpper;              // op(A) is upper triangular: A[m][k] taken as 0 for k < m (not read);
+                           // 2: strictly upper (also 0 for k == m)
   int bUpper;              // op(B) is upper triangular: B[k][n] taken as 0 for k > n (not read)
+  int aLower;              // op(A) is lower triangular: A[m][k] taken as 0 for k > m (not read)
+  // Global K index of this launch's K index 0 for the triangular masks (products split over K):
+  // kofs, plus kofs2 for each step of the second batch index (see batch2).  kend_glob > 0: the
+  // global K range ends there (a split whose last slice is shorter than K).
+  int kofs, kofs2, kend_glob;
   const double *skip_if_le;  // if set and *skip_if_le <= skip_thr, the launch does nothing
   double skip_thr;
   long sIdxA, sIdxB;       // batch stride of idxA / idxB (0: one index list for all entries)
@@ -47,6 +54,8 @@ struct GemmDesc {
   // Workgroup -> tile order, set by zgemm from the calling thread's choice
   // (set_gemm_tile_order): 0 XCD-grouped, 1 plain linear.
   int linear_order;
+  // Nonzero: large tiles are allowed from K = 64 on (rank-64 updates of a large result).
+  int short_k_large;
 };
 
 hipError_t zgemm(const GemmDesc &g, hipStream_t s);

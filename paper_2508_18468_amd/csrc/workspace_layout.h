@@ -42,10 +42,10 @@ inline long trd_panel_elems(int n) {
 // progress words and counters of the bulge chase.
 constexpr int TRD2_SB = 32;
 constexpr int TRD2_RPW = 128;
-constexpr int TRD2_KS = 16;
+constexpr int TRD2_KS = 64;
 MFQ_LAYOUT_HD inline int trd2_groups(int n) { return (n - TRD2_SB + TRD2_RPW - 1) / TRD2_RPW; }
-// K-split partials: n^2 / 8 + n entries (the m x TRD2_SB product takes at most m / 512 slices)
-// or TRD2_KS slices of a TRD2_SB x TRD2_SB block, whichever is larger.
+// K-split partials: n^2 / 8 + n entries (the two m x TRD2_SB products take at most
+// n^2 / (512 m) slices each) or TRD2_KS slices of a TRD2_SB x TRD2_SB block, whichever is larger.
 MFQ_LAYOUT_HD inline long trd2_kp_elems(int n) {
   const long a = (long)n * n / 8 + n, b = (long)TRD2_KS * TRD2_SB * TRD2_SB;
   return a > b ? a : b;

@@ -19,7 +19,8 @@
 //              bytes per flop of the small tile, 64 accumulator doubles per
 //              lane (more per wave would overflow the register file);
 //   128 x 64,  4 waves, 64 x 32 per wave   the other large products with
-//              op(A) = A and a general result (the products with R^-1 among them).
+//              op(A) = A and a general result (the products with R^-1 among them);
+//   64 x 32 and 32 x 32, 2 waves           results at most 32 columns wide.
 // K advances in chunks of 16; the next chunk is fetched into registers while the
 // current one feeds the matrix cores.  Products with op(A) = A (the propagator among
 // them) store it into their one LDS buffer between two barriers (66 KiB for
@@ -199,15 +200,24 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   }
   const int m0 = tm * MT, n0 = tn * NT;
   if (g.tri == TRI_UPPER && m0 > n0 + NT - 1) return;  // tile entirely below the diagonal
+  if (g.tri == TRI_LOWER && n0 > m0 + MT - 1) return;  // tile entirely above the diagonal
+  // global K index of local index 0 (the triangular masks compare it with m and n)
+  const int kg0 = g.kofs + (g.batch2 > 1 ? (b % g.batch2) * g.kofs2 : 0);
   int kbeg = 0, kend = g.K;
-  if (g.aUpper) kbeg = (m0 / KT) * KT;
-  if (g.bUpper) kend = min(g.K, n0 + NT);
+  if (g.aUpper && m0 > kg0) kbeg = ((m0 - kg0) / KT) * KT;
+  if (g.bUpper) kend = min(kend, max(0, n0 + NT - kg0));
+  if (g.aLower) kend = min(kend, max(0, m0 + MT - kg0));
+  if (g.kend_glob > 0) kend = min(kend, max(0, g.kend_glob - kg0));
 
   // Two buffers for the Gram-shaped products (op(A) = A^+) and the reduction epilogues: the
   // next chunk is stored into the idle buffer after the current one's first k-step, and one
   // barrier per chunk remains (Gram U^+U at L = 1024, N = 512, 384 trajectories: 0.667 ->
   // 0.695 of the FP64 peak).  The propagator product gains nothing from it and keeps one.
   constexpr int NBUF = ((FL & (FL_SQSUM | FL_DIAG)) != 0 || OPA == OP_C) ? 2 : 1;
+  // k-step after which the next chunk is stored into the idle buffer: early for the large tiles
+  // (the store overlaps the chunk's matrix-core work), late for the 32-column tiles, whose few
+  // workgroups per compute unit cannot hide a load that must land after one k-step
+  constexpr int STORE_KK = NT <= 32 ? KT - 4 : 4;
   __shared__ double Ar[NBUF][KT][MT + PAD], Ai[NBUF][KT][MT + PAD];
   __shared__ double Br[NBUF][KT][NT + PAD], Bi[NBUF][KT][NT + PAD];
 
@@ -236,7 +246,10 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPA == OP_N ? a_slow + DA * i : a_fast;
       const int gm = m0 + m, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if ((!EDGE || (gm < g.M && gk < kend)) && !((FL & FL_MASK) && g.aUpper && gk < gm)) {
+      const int kgl = gk + kg0;  // global K index
+      const bool zero = (FL & FL_MASK) && ((g.aUpper && (kgl < gm || (g.aUpper == 2 && kgl == gm))) ||
+                                           (g.aLower && kgl > gm));
+      if ((!EDGE || (gm < g.M && gk < kend)) && !zero) {
         cplx v;
         if (OPA == OP_N) {
           const long row = idxA ? idxA[gm] : gm;
@@ -256,7 +269,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       const int k = OPB == OP_N ? b_fast : b_slow + DB * i;
       const int gn = n0 + n, gk = k0 + k;
       double re = 0.0, im = 0.0;
-      if ((!EDGE || (gn < g.N && gk < kend)) && !((FL & FL_MASK) && g.bUpper && gk > gn)) {
+      if ((!EDGE || (gn < g.N && gk < kend)) && !((FL & FL_MASK) && g.bUpper && gk + kg0 > gn)) {
         cplx v;
         if (OPB == OP_N) {
           const long row = idxB ? idxB[gk] : gk;
@@ -309,7 +322,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       // the idle buffer was last read in the previous chunk, before its closing barrier
-      if (NBUF == 2 && kk == 4 && it + 1 < nk) store(buf ^ 1);
+      if (NBUF == 2 && kk == STORE_KK && it + 1 < nk) store(buf ^ 1);
       const int k = kk + (lane >> 4);
       double a_re[IM], a_im[IM], b_re[JN], b_im[JN];
 #pragma unroll
@@ -370,6 +383,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
         const int col = n0 + wc * (NT / WN) + j * 16 + (lane & 15);
         if (EDGE && (row >= g.M || col >= g.N)) continue;
         if (g.tri == TRI_UPPER && row > col) continue;
+        if (g.tri == TRI_LOWER && row < col) continue;
         const double xr = acc_re[i][j][r], xi = acc_im[i][j][r];
         double yr = g.alpha.re * xr - g.alpha.im * xi;
         double yi = g.alpha.re * xi + g.alpha.im * xr;
@@ -436,7 +450,7 @@ unsigned grid_size(const GemmDesc &g) {
 template <int MT, int NT>
 bool needs_edge(const GemmDesc &g) {
   constexpr int KT = kchunk<MT>();
-  return (g.M % MT) || (g.N % NT) || (g.K % KT);
+  return (g.M % MT) || (g.N % NT) || (g.K % KT) || (g.kend_glob % KT);
 }
 
 template <int MT, int NT, bool GATHER, bool EDGE, int FL = 0>
@@ -469,7 +483,7 @@ void launch_wide_ops(const GemmDesc &g, hipStream_t s) {
   const bool edge = needs_edge<128, 64>(g);
   if (g.idxA || g.idxB)
     hipLaunchKernelGGL((zgemm_wide_kernel<OPB, true, true, 0>), grid, block, 0, s, g);
-  else if (g.aUpper || g.bUpper) {
+  else if (g.aUpper || g.bUpper || g.aLower) {
     if (edge) hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, true, FL_MASK>), grid, block, 0, s, g);
     else hipLaunchKernelGGL((zgemm_wide_kernel<OPB, false, false, FL_MASK>), grid, block, 0, s, g);
   } else if (edge) {
@@ -485,13 +499,33 @@ hipError_t launch_wide(const GemmDesc &g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Results at most 32 columns wide (the panels of the band reduction: m x 32 products and the
+// deep 32 x 32 ones split over K) take two-wave tiles of 64 x 32 or 32 x 32: a 64 x 64 tile
+// would spend half its matrix-core work on zero columns.
+template <int MT, int NT>
+hipError_t launch_thin(const GemmDesc &g, hipStream_t s) {
+  const dim3 grid(grid_size<MT, NT>(g));
+  const bool edge = needs_edge<MT, NT>(g);
+  if (g.idxA || g.idxB) {
+    launch_ops<MT, NT, true, true>(g, grid, s);
+  } else if (g.aUpper || g.bUpper || g.aLower) {
+    if (edge) launch_ops<MT, NT, false, true, FL_MASK>(g, grid, s);
+    else launch_ops<MT, NT, false, false, FL_MASK>(g, grid, s);
+  } else if (edge) {
+    launch_ops<MT, NT, false, true>(g, grid, s);
+  } else {
+    launch_ops<MT, NT, false, false>(g, grid, s);
+  }
+  return hipGetLastError();
+}
+
 template <int MT, int NT>
 hipError_t launch(const GemmDesc &g, hipStream_t s) {
   const dim3 grid(grid_size<MT, NT>(g));
   const dim3 block(nthreads<NT>());
   const bool edge = needs_edge<MT, NT>(g);
   if (g.part) {  // reduction epilogues: products U_X U_Y^+ only
-    if (g.opA != OP_N || g.opB != OP_C || g.R1 || g.aUpper || g.bUpper) return hipErrorInvalidValue;
+    if (g.tri == TRI_LOWER || g.opA != OP_N || g.opB != OP_C || g.R1 || g.aUpper || g.bUpper || g.aLower) return hipErrorInvalidValue;
     if (g.tri == TRI_UPPER) {
       if (g.M != g.N || g.idxA || g.idxB) return hipErrorInvalidValue;
       if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_N, OP_C, MT, NT, false, true, FL_DIAG>), grid, block, 0, s, g);
@@ -506,14 +540,15 @@ hipError_t launch(const GemmDesc &g, hipStream_t s) {
     return hipGetLastError();
   }
   if (g.R1) {  // near-identity epilogue: the upper Gram U^+ U of a Cholesky-QR pass
-    if (g.opA != OP_C || g.opB != OP_N || g.idxA || g.idxB || g.aUpper || g.bUpper) return hipErrorInvalidValue;
+    if (g.opA != OP_C || g.opB != OP_N || g.idxA || g.idxB || g.aUpper || g.bUpper || g.aLower)
+      return hipErrorInvalidValue;
     if (edge) hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, false, true, FL_NEAR_ID>), grid,
                                  dim3(nthreads<NT>()), 0, s, g);
     else hipLaunchKernelGGL((zgemm_kernel<OP_C, OP_N, MT, NT, false, false, FL_NEAR_ID>), grid,
                             dim3(nthreads<NT>()), 0, s, g);
   } else if (g.idxA || g.idxB) {
     launch_ops<MT, NT, true, true>(g, grid, s);
-  } else if (g.aUpper || g.bUpper) {
+  } else if (g.aUpper || g.bUpper || g.aLower) {
     if (edge) launch_ops<MT, NT, false, true, FL_MASK>(g, grid, s);
     else launch_ops<MT, NT, false, false, FL_MASK>(g, grid, s);
   } else if (edge) {
@@ -552,7 +587,7 @@ hipError_t zgemm_propagator(const GemmDesc &g0, hipStream_t s) {
 int pick_tile(const GemmDesc &g) {
   if (tl_tile_mode == GEMM_TILE_SMALL) return 64;
   const long work = (long)g.M * g.N * g.batch;
-  if (g.M >= 128 && g.N >= 128 && g.K >= 128 &&
+  if (g.M >= 128 && g.N >= 128 && g.K >= (g.short_k_large ? 64 : 128) &&
       (tl_tile_mode == GEMM_TILE_LARGE || work >= (1L << 22)))
     return 128;
   return 64;
@@ -562,6 +597,8 @@ hipError_t zgemm(const GemmDesc &g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return hipSuccess;
   GemmDesc g = g0;
   g.linear_order = tl_tile_order;
+  if (g.N <= 32 && !g.part && !g.R1 && g.tri != TRI_UPPER)  // thin results: no idle tile columns
+    return g.M <= 32 ? launch_thin<32, 32>(g, s) : launch_thin<64, 32>(g, s);
   if (pick_tile(g) != 128) return launch<64, 64>(g, s);
   if (g.opA == OP_N && g.tri != TRI_UPPER && !g.part && !g.R1) return launch_wide(g, s);
   return launch<128, 128>(g, s);
@@ -622,7 +659,7 @@ hipError_t zgemm_ring_bins(const GemmDesc &g, int L, double *out, hipStream_t s)
 }
 
 hipError_t zgemm_tile_sum(const GemmDesc &g, double *out, hipStream_t s) {
-  if (!g.part || g.tri == TRI_UPPER) return hipErrorInvalidValue;
+  if (!g.part || g.tri != TRI_NONE) return hipErrorInvalidValue;
   hipError_t e = zgemm(g, s);
   if (e != hipSuccess) return e;
   const long T = pick_tile(g), n_tiles = ((g.M + T - 1) / T) * ((g.N + T - 1) / T);
