@@ -366,8 +366,8 @@ mfq_status mfq_set_pm_path(mfq_ctx *ctx, int32_t path);
  *                      through progress words (a wait beyond 10 s makes the call return
  *                      MFQ_EDEVICE); used for orders >= 66 where the Rinv region holds its
  *                      storage (n^2 / 8 + 160 n complex entries per trajectory, at least about
- *                      20000), else one stage;
- *   MFQ_EIG_AUTO       two stages from order 6144 on, one below (default; measured on the
+ *                      16000), else one stage;
+ *   MFQ_EIG_AUTO       two stages from order 4096 on, one below (default; measured on the
  *                      MI355X, two stages are faster from about that order). */
 #define MFQ_EIG_AUTO 0
 #define MFQ_EIG_ONE_STAGE 1

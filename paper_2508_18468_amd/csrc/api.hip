@@ -274,6 +274,10 @@ mfq_status check_flag(mfq_ctx *c) {
       return fail(c, MFQ_EDEVICE, "tridiagonal reduction: a bulge-chase dependency wait exceeded its limit "
                                   "(trajectory " + std::to_string(info.traj) + ", sweep " +
                                   std::to_string(info.col) + ")");
+    if (info.set && info.source == 5)
+      return fail(c, MFQ_EDEVICE, "band reduction: a wait for the other workgroups of a panel exceeded its "
+                                  "limit (trajectory " + std::to_string(info.traj) + ", column " +
+                                  std::to_string(info.col) + ")");
     static const char *src[] = {"unknown source", "Cholesky-QR pass 1", "Cholesky-QR pass 2", "fused kernel"};
     char where[192] = "";
     if (info.set)

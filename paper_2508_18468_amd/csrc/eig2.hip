@@ -9,9 +9,11 @@
 // then the band is reduced to tridiagonal form by bulge chasing, whose work is O(n^2 TRD2_SB):
 //
 //   stage 1, per panel of TRD2_SB columns starting at column j (rows below the band:
-//     m = n - j - TRD2_SB): Householder QR of the m x TRD2_SB panel, one launch per column
-//     (rows spread over the grid; every workgroup reduces the per-workgroup column statistics
-//     of the previous launch in the same fixed order, so all of them form the same reflector),
+//     m = n - j - TRD2_SB): Householder QR of the m x TRD2_SB panel, column by column (rows
+//     spread over the grid; every workgroup reduces the per-workgroup column statistics of the
+//     previous column in the same fixed order, so all of them form the same reflector) in one
+//     kernel whose workgroups meet at a counter before each column, or one launch per column
+//     where that grid would not fit the GPU at once,
 //     leaving R in the band and zeros below it; then with Q = I - V T V^+ (compact WY),
 //     A22 <- Q^+ A22 Q = A22 - V W^+ - W V^+,  W = X - (1/2) V (T^+ (V^+ X)),  X = A22 (V T),
 //     the deep products split over K into slices summed in a fixed order.  Only the lower
@@ -31,6 +33,8 @@
 // Reflectors are Hermitian, H = I - tau v v^+ with real tau (make_reflector), formed from the
 // vector scaled by its largest component.  The final tridiagonal has complex sub-diagonal
 // entries; a diagonal unitary similarity makes them |e_i| without changing the spectrum.
+#include <atomic>
+
 #include "device_common.h"
 
 namespace mfq {
@@ -45,7 +49,8 @@ constexpr int KS_MAX = TRD2_KS;   // K slices of the deep products
 // Per-matrix scratch inside EigWork::panel (complex units from the matrix's base).
 struct Scratch {
   cplx *X, *Y, *VT, *KP, *S, *T, *Z, *M2, *TAU, *PAY;
-  int *prog;   // n progress words, the sweep counter at prog[n], the abort word at prog[n + 1]
+  int *prog;   // n progress words, the sweep counter at prog[n], the abort word at prog[n + 1],
+               // the panel counter of stage 1 at prog[n + 2]
 };
 __host__ __device__ inline Scratch scratch_of(cplx *base, int n, int g1) {
   Scratch s;
@@ -81,8 +86,8 @@ __device__ __forceinline__ double wsum(double x) {
 // Statistics of workgroup g for column c: its largest |x_i| over rows i >= c (s_g), the sum of
 // |x_i / s_g|^2 over rows i > c, the sums conj(x_i / s_g) P[i, c'] over rows i > c for every
 // c' > c, and, from the workgroup holding row c, the pivot row P[c, c'] (c' >= c).
-__global__ __launch_bounds__(256) void p1_col_kernel(EigWork W, int n, int j, int m, int k, int kmax, int g1,
-                                                     int gm) {
+__device__ __forceinline__ void p1_col_step(const EigWork &W, int n, int j, int m, int k, int kmax, int g1,
+                                            int gm) {
   const int b = blockIdx.y, g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   cplx *A = W.A + (long)b * n * n;
   cplx *P = A + (j + SB) + (long)j * n;  // panel: rows 0 .. m-1, columns 0 .. SB-1, ld n
@@ -284,6 +289,64 @@ __global__ __launch_bounds__(256) void p1_col_kernel(EigWork W, int n, int j, in
   }
 }
 
+__global__ __launch_bounds__(256) void p1_col_kernel(EigWork W, int n, int j, int m, int k, int kmax, int g1,
+                                                     int gm) {
+  p1_col_step(W, n, j, m, k, kmax, g1, gm);
+}
+
+// All column launches of one panel as one kernel: before column k (k >= 0) every workgroup
+// waits until all gm workgroups of its matrix have finished column k - 1, counted on a
+// per-matrix counter that started the panel at `base` (the statistics that column k reduces
+// are then complete, and the buffer that column k overwrites is no longer read).  Workgroups
+// therefore depend on workgroups that may not have started: the host launches this kernel only
+// when the grid fits the GPU at once.  A wait longer than `limit` wall-clock ticks sets the abort
+// word and the context's error flag, and every workgroup leaves.
+__global__ __launch_bounds__(256) void p1_panel_kernel(EigWork W, int n, int j, int m, int kmax, int g1, int gm,
+                                                       int base, long long limit) {
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const Scratch sc = scratch_of(W.panel + (long)b * W.panel_stride, n, g1);
+  int *ctr = sc.prog + n + 2, *abort_w = sc.prog + n + 1;
+  __shared__ int s_go;
+  for (int k = -1; k < kmax; ++k) {
+    if (k >= 0) {
+      if (tid == 0) {
+        int go = 1;
+        const int need = base + gm * (k + 1);
+        long long t0 = -1;
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            go = 0;
+            break;
+          }
+          const long long now = wall_clock64();
+          if (t0 < 0) t0 = now;
+          if (now - t0 > limit) {
+            __hip_atomic_store(abort_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(W.flag, 1);
+            if (atomicCAS(&W.info->set, 0, 1) == 0) {
+              W.info->source = 5;
+              W.info->traj = b;
+              W.info->col = j + k;
+              W.info->pivot = 0.0;
+            }
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_go = go;
+      }
+      __syncthreads();
+      if (!s_go) return;
+    }
+    p1_col_step(W, n, j, m, k, kmax, g1, gm);
+    // the barrier completes every wave's stores of column k, thread 0 releases them
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // T of the panel's compact-WY factor from the Gram S = V^+ V: T_kk = tau_k,
 // T[0:k, k] = -tau_k T[0:k, 0:k] S[0:k, k]; thread i owns row i of T (in LDS, beside S).
 // Zeros below the diagonal.
@@ -348,10 +411,10 @@ constexpr int CH_THREADS = 256;
 
 __device__ __forceinline__ int ntask(int n, int j) { return (n - 2 - j) / SB + 1; }
 
-// Progress words, the sweep counter and the abort word of every matrix.
+// Progress words, the sweep counter, the abort word and the panel counter of every matrix.
 __global__ __launch_bounds__(256) void p2_clear_kernel(EigWork W, int n, int g1) {
   const Scratch sc = scratch_of(W.panel + (long)blockIdx.y * W.panel_stride, n, g1);
-  for (int i = blockIdx.x * 256 + threadIdx.x; i <= n + 1; i += gridDim.x * 256) sc.prog[i] = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i <= n + 2; i += gridDim.x * 256) sc.prog[i] = 0;
 }
 
 // One task's entries are loaded into registers at once, so that a task costs about one memory
@@ -605,11 +668,28 @@ GemmDesc gdesc() {
 
 int groups_for(int n) { return trd2_groups(n); }
 
-// K slices for a product with `tiles` output tiles per matrix and depth K: at most `wgs`
-// workgroups in all, slices at least `depth` deep.
-int kslices(long tiles, int K, int B, long wgs, int depth) {
+// Workgroups of p1_panel_kernel that the current GPU holds at once (0 if unknown).
+long panel_capacity() {
+  static std::atomic<long> cap[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  long c = cap[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, p1_panel_kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    c = per_cu > 0 && cus > 0 ? (long)per_cu * cus : -1;
+    cap[dev].store(c, std::memory_order_relaxed);
+  }
+  return c > 0 ? c : 0;
+}
+
+// K slices for a product with `tiles` output tiles per matrix and depth K: at most `ksmax`, at
+// most `wgs` workgroups in all, slices at least `depth` deep.
+int kslices(long tiles, int K, int B, long wgs, int depth, int ksmax) {
   int ks = 1;
-  while (ks < KS_MAX && tiles * B * ks * 2 <= wgs && K / (2 * ks) >= depth) ks *= 2;
+  while (ks * 2 <= ksmax && tiles * B * ks * 2 <= wgs && K / (2 * ks) >= depth) ks *= 2;
   return ks;
 }
 
@@ -642,15 +722,27 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
   hipError_t e;
   const Scratch s0 = scratch_of(w.panel, n, g1);  // matrix 0; the others at multiples of panel_stride
   const long ps = w.panel_stride, nn = (long)n * n;
+  const long cap = panel_capacity();
+  int base = 0;  // the panel counter's value at the start of the next panel kernel
+  hipLaunchKernelGGL(p2_clear_kernel, dim3((n + 256) / 256, B), dim3(256), 0, s, w, n, g1);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   for (int j = 0; n - j - SB >= 2; j += SB) {
     const int m = n - j - SB, kmax = std::min(m, SB), gm = (m + P1_RPW - 1) / P1_RPW;
     cplx *A22 = w.A + (j + SB) + (long)(j + SB) * n;
-    for (int k = -1; k < kmax; ++k) {
-      hipLaunchKernelGGL(p1_col_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, k, kmax, g1, gm);
+    if ((long)gm * B <= cap / 2) {  // half of what the GPU holds at once: room for other streams
+      hipLaunchKernelGGL(p1_panel_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, kmax, g1, gm, base,
+                         wait_ticks);
       if ((e = hipGetLastError()) != hipSuccess) return e;
+      base += gm * (kmax + 1);
+    } else {
+      for (int k = -1; k < kmax; ++k) {
+        hipLaunchKernelGGL(p1_col_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, k, kmax, g1, gm);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
     }
     {  // S = V^+ V
-      const int ks = slice_count(m, kslices(1, m, B, 512, 64));
+      const int ks = slice_count(m, kslices(1, m, B, 512, 64, trd2_ks_max(n)));
+      if ((long)ks * SB * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;
       g.A = s0.X; g.lda = n; g.sA = ps; g.opA = OP_C;
@@ -673,9 +765,10 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
     }
     {  // X = A22 (V T) from the lower triangle of A22: tril(A22) (V T) + striu(A22^+) (V T),
        // each split over K, all partials summed into the W columns of X
-      int ks = kslices((m + 63) / 64, m, B, 4096, 128);
+      int ks = kslices((m + 63) / 64, m, B, 4096, 128, KS_MAX);
       while (ks > 1 && 2L * ks * m * SB > trd2_kp_elems(n)) ks /= 2;
       ks = slice_count(m, ks);
+      if (2L * ks * m * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = m; g.N = SB; g.batch = B;
       g.A = A22; g.lda = n; g.sA = nn; g.opA = OP_N; g.aLower = 1;
@@ -690,7 +783,8 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {  // Z = V^+ X
-      const int ks = slice_count(m, kslices(1, m, B, 512, 64));
+      const int ks = slice_count(m, kslices(1, m, B, 512, 64, trd2_ks_max(n)));
+      if ((long)ks * SB * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;
       g.A = s0.X; g.lda = n; g.sA = ps; g.opA = OP_C;

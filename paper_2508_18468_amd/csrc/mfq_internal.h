@@ -280,7 +280,7 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
 // Reduction form of tridiagonalize for the calling thread: AUTO (by size), ONE_STAGE, TWO_STAGE
 // (where it applies).  Set by the context around its launches.
 enum { EIG_PATH_AUTO = 0, EIG_PATH_ONE_STAGE = 1, EIG_PATH_TWO_STAGE = 2 };
-constexpr int TRD2_AUTO_MIN = 6144;  // AUTO takes the two-stage form from this order on
+constexpr int TRD2_AUTO_MIN = 4096;  // AUTO takes the two-stage form from this order on
 void set_eig_path(int mode);
 int eig_path();
 hipError_t bisect_eigvals(const EigWork &w, int n, int B, hipStream_t s);

@@ -39,16 +39,24 @@ inline long trd_panel_elems(int n) {
 // storage in the Rinv region (complex entries): X = [V W] and Y = [W V] (n x 2 TRD2_SB each),
 // V T (n x TRD2_SB), the K-split partials, four TRD2_SB^2 blocks (V^+ V, T, V^+ X, T^+ V^+ X),
 // tau, the column statistics of the column launches (two per workgroup), and n + 64 ints of
-// progress words and counters of the bulge chase.
+// progress words and counters of the bulge chase and the panel kernel.
 constexpr int TRD2_SB = 32;
 constexpr int TRD2_RPW = 128;
 constexpr int TRD2_KS = 64;
 MFQ_LAYOUT_HD inline int trd2_groups(int n) { return (n - TRD2_SB + TRD2_RPW - 1) / TRD2_RPW; }
-// K-split partials: n^2 / 8 + n entries (the two m x TRD2_SB products take at most
-// n^2 / (512 m) slices each) or TRD2_KS slices of a TRD2_SB x TRD2_SB block, whichever is larger.
+// Most K slices of the deep TRD2_SB x TRD2_SB products of an order-n reduction (one per 128
+// rows, at most TRD2_KS).
+MFQ_LAYOUT_HD inline int trd2_ks_max(int n) {
+  const int k = n / 128;
+  return k < 1 ? 1 : (k > TRD2_KS ? TRD2_KS : k);
+}
+// K-split partials, the largest of: n^2 / 8 + n entries (the two m x TRD2_SB products of X take
+// up to n^2 / (512 m) slices each), one slice of each of them (2 TRD2_SB n), and trd2_ks_max(n)
+// slices of a TRD2_SB x TRD2_SB block.
 MFQ_LAYOUT_HD inline long trd2_kp_elems(int n) {
-  const long a = (long)n * n / 8 + n, b = (long)TRD2_KS * TRD2_SB * TRD2_SB;
-  return a > b ? a : b;
+  const long a = (long)n * n / 8 + n, b = (long)trd2_ks_max(n) * TRD2_SB * TRD2_SB, c = 2L * TRD2_SB * n;
+  const long ab = a > b ? a : b;
+  return ab > c ? ab : c;
 }
 MFQ_LAYOUT_HD inline long trd2_scratch_elems(int n) {
   return (long)n * 5 * TRD2_SB + trd2_kp_elems(n) + 4L * TRD2_SB * TRD2_SB + TRD2_SB +
@@ -66,7 +74,8 @@ inline int cont_jcap(int Lx, int Ly) {
 struct BreakdownInfo {
   int32_t set;     // 0 until a breakdown is recorded
   int32_t source;  // 1: Cholesky-QR pass 1, 2: pass 2, 3: fused small-lattice kernel,
-                   // 4: a dependency wait of the bulge chase exceeded its limit (no pivot)
+                   // 4: a dependency wait of the bulge chase exceeded its limit (no pivot),
+                   // 5: a panel wait of the band reduction exceeded its limit (no pivot)
   int32_t traj;    // trajectory (batch index) of the pivot
   int32_t col;     // column of the pivot in the N x N Gram
   double pivot;    // its value (non-positive or not finite)

@@ -103,6 +103,13 @@ int main() {
     check(s, false);
     check(s, true);
   }
+  // K-split partials of the two-stage reduction: one slice of both halves of X = A22 (V T) (m
+  // rows, m <= n - TRD2_SB) and the most slices of the deep TRD2_SB x TRD2_SB products
+  const char *name = "two-stage partials";
+  for (int n = 2 * TRD2_SB + 2; n <= 70000; n += (n < 2048 ? 1 : 97)) {
+    CHECK(trd2_kp_elems(n) >= 2L * TRD2_SB * (n - TRD2_SB));
+    CHECK(trd2_kp_elems(n) >= (long)trd2_ks_max(n) * TRD2_SB * TRD2_SB);
+  }
   if (failures) {
     std::printf("%d failures\n", failures);
     return 1;
