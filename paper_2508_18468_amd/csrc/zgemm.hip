@@ -212,12 +212,11 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
   // Two buffers for the Gram-shaped products (op(A) = A^+) and the reduction epilogues: the
   // next chunk is stored into the idle buffer after the current one's first k-step, and one
   // barrier per chunk remains (Gram U^+U at L = 1024, N = 512, 384 trajectories: 0.667 ->
-  // 0.695 of the FP64 peak).  The propagator product gains nothing from it and keeps one.
-  constexpr int NBUF = ((FL & (FL_SQSUM | FL_DIAG)) != 0 || OPA == OP_C) ? 2 : 1;
-  // k-step after which the next chunk is stored into the idle buffer: early for the large tiles
-  // (the store overlaps the chunk's matrix-core work), late for the 32-column tiles, whose few
-  // workgroups per compute unit cannot hide a load that must land after one k-step
-  constexpr int STORE_KK = NT <= 32 ? KT - 4 : 4;
+  // 0.695 of the FP64 peak).  The propagator product gains nothing from it and keeps one, and
+  // so do the 32-column tiles, whose load must then land only at the end of the chunk and
+  // whose single buffer lets four workgroups share a compute unit (the conjugate half of the
+  // band reduction's X: 93 -> 82 ms per two 8192-site Grams).
+  constexpr int NBUF = ((FL & (FL_SQSUM | FL_DIAG)) != 0 || (OPA == OP_C && NT > 32)) ? 2 : 1;
   __shared__ double Ar[NBUF][KT][MT + PAD], Ai[NBUF][KT][MT + PAD];
   __shared__ double Br[NBUF][KT][NT + PAD], Bi[NBUF][KT][NT + PAD];
 
@@ -322,7 +321,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4) {
       // the idle buffer was last read in the previous chunk, before its closing barrier
-      if (NBUF == 2 && kk == STORE_KK && it + 1 < nk) store(buf ^ 1);
+      if (NBUF == 2 && kk == 4 && it + 1 < nk) store(buf ^ 1);
       const int k = kk + (lane >> 4);
       double a_re[IM], a_im[IM], b_re[JN], b_im[JN];
 #pragma unroll
