@@ -276,18 +276,25 @@ mfq_status mfq_run(mfq_ctx *ctx, int32_t protocol, const double *gamma, double d
                    int32_t n_steps, int32_t obs_every, const int32_t *region, int32_t n_sites,
                    double *S_host, int32_t *n_obs_out);
 
-/* Several contexts in ONE launch of the fused kernel (execution form: trajectories of
- * uneven lattices, protocols and monitoring rates batched into one persistent launch).
+/* Several contexts advanced together (execution form: trajectories of uneven lattices,
+ * protocols and monitoring rates batched into one launch or one graph).
  * ctx[k] runs args[k].n_steps steps of its own protocol, gamma (n_traj host doubles), dt and
  * seed, with S of its own region observed after every step whose absolute index is a
  * multiple of obs_every (0: none) into args[k].S_host (n_obs x n_traj doubles, observation-
- * major; args[k].n_obs is set on return).  Each workgroup finds its context in a table and
- * runs one trajectory with its state in LDS, exactly as mfq_run on the fused path does
- * (same random numbers, same results).  1 <= n <= 8 distinct contexts on one device, each of
- * which must fit the fused path (split-step integrator).  The launch is enqueued on ctx[0]'s
- * stream after the work already queued on the others' streams; the call synchronises.
- * Errors: MFQ_EINVAL (as mfq_run, too many or repeated contexts, different devices),
- * MFQ_ESTATE, MFQ_ENUMERIC (per context, the first one reported), MFQ_EDEVICE. */
+ * major; args[k].n_obs is set on return).  1 <= n <= 8 distinct contexts on one device.
+ * When every context fits the fused path (split-step integrator): ONE launch of the fused
+ * kernel, each workgroup finding its context in a table and running one trajectory with its
+ * state in LDS, exactly as mfq_run on the fused path does (same random numbers, same
+ * results), enqueued on ctx[0]'s stream after the work already queued on the others' streams.
+ * Otherwise every context takes its per-phase kernels: ONE graph holds two steps of every
+ * context, each context on a parallel branch, and is replayed while all of them have two
+ * steps left before their next observation or their end; the other steps run per context on
+ * its own stream.  The results equal mfq_run of each context alone (same kernels, same random
+ * numbers).  This form needs steps that a graph can hold: no blocked projective measurement
+ * (mfq_set_pm_path), graphs enabled and profiling off.  The call synchronises.
+ * Errors: MFQ_EINVAL (as mfq_run, too many or repeated contexts, different devices, steps a
+ * graph cannot hold), MFQ_ESTATE, MFQ_ENUMERIC (per context, the first one reported),
+ * MFQ_ENOMEM (RK4 scratch), MFQ_EDEVICE. */
 typedef struct {
   int32_t protocol;
   const double *gamma;

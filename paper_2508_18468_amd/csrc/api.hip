@@ -13,6 +13,8 @@
 #include <vector>
 
 #include "../../include/mfq.h"
+#include <algorithm>
+
 #include "mfq_internal.h"
 
 using namespace mfq;
@@ -572,6 +574,189 @@ mfq_status ensure_step_graph(mfq_ctx *c, int protocol, double dt, uint64_t seed)
   return MFQ_OK;
 }
 
+// Contexts of one mfq_run_group call that advance through their per-phase kernels: one graph
+// holds two steps of every member context, each on a branch of its own (a side stream joined
+// to the capture), so that the contexts' kernels can overlap; it is replayed while every
+// member has two steps left before its next stop (its last step or an observation).  Steps
+// outside such pairs run per context, and each context observes on its own schedule.
+struct GroupRun {
+  mfq_ctx *const *ctxs;
+  const mfq_run_args *args;
+  int n;
+  std::vector<hipStream_t> side;  // one per context, and the origin of the capture at [n]
+  std::vector<hipEvent_t> evs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> key;           // members and their buffer parity when the graph was captured
+  ~GroupRun() {
+    for (hipStream_t st : side) (void)hipStreamSynchronize(st);
+    drop();
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+    for (hipStream_t st : side) (void)hipStreamDestroy(st);
+  }
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+  hipEvent_t event(size_t i) { return evs[i]; }
+};
+
+// Capture two steps of each member context into one graph on the origin stream.
+mfq_status capture_group(GroupRun &g, const std::vector<int> &members) {
+  mfq_ctx *c = g.ctxs[members[0]];
+  hipStream_t origin = g.side[g.n];
+  g.drop();
+  HIPCHK(hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed), "begin group capture");
+  hipError_t e = hipEventRecord(g.event(0), origin);
+  mfq_status st = MFQ_OK;
+  for (size_t i = 0; i < members.size() && e == hipSuccess && !st; ++i) {
+    mfq_ctx *ck = g.ctxs[members[i]];
+    const mfq_run_args &r = g.args[members[i]];
+    hipStream_t sk = g.side[members[i]];
+    if ((e = hipStreamWaitEvent(sk, g.event(0), 0)) != hipSuccess) break;
+    TileScope tiles(ck);
+    hipStream_t own = ck->stream;
+    const int cur0 = ck->cur;
+    ck->stream = sk;
+    st = enqueue_step(ck, r.protocol, r.dt, r.seed, 1);
+    if (!st) st = enqueue_step(ck, r.protocol, r.dt, r.seed, 2);
+    if (!st) e = set_step(ck->step_dev, 2, true, sk);
+    ck->stream = own;
+    ck->cur = cur0;
+    if (!st && e == hipSuccess && (e = hipEventRecord(g.event(1 + members[i]), sk)) == hipSuccess)
+      e = hipStreamWaitEvent(origin, g.event(1 + members[i]), 0);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(origin, &graph);
+  if (st || e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st) return st;
+    return hip_fail(c, e != hipSuccess ? e : e2, "group capture");
+  }
+  g.graph = graph;
+  HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "group graph instantiate");
+  for (int k : members) {
+    g.key.push_back(k);
+    g.key.push_back(g.ctxs[k]->cur);
+  }
+  return MFQ_OK;
+}
+
+mfq_status run_group_graph(mfq_ctx *const *ctxs, const mfq_run_args *args, int n) {
+  mfq_ctx *c = ctxs[0];
+  GroupRun g;
+  g.ctxs = ctxs;
+  g.args = args;
+  g.n = n;
+  HIPCHK(hipSetDevice(c->device), "hipSetDevice");
+  for (int k = 0; k <= n; ++k) {
+    hipStream_t st = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream create");
+    g.side.push_back(st);
+  }
+  for (int k = 0; k < n + 2; ++k) {  // fork, one join per context, the group's completion
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+    g.evs.push_back(ev);
+  }
+  std::vector<hipEvent_t> ready(n, nullptr);
+  for (int k = 0; k < n; ++k) {
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event create");
+    g.evs.push_back(ev);
+    ready[k] = ev;
+  }
+  std::vector<int> left(n), k_obs(n, 0);
+  for (int k = 0; k < n; ++k) {
+    mfq_ctx *ck = ctxs[k];
+    mfq_status st = prepare_step(ck, args[k].gamma, args[k].dt);
+    if (!st && args[k].protocol == MFQ_HOMODYNE && ck->integrator == MFQ_INTEGRATOR_RK4) st = ensure_rk4(ck);
+    if (st) return st;
+    left[k] = args[k].n_steps;
+  }
+  // steps of context k before its next stop
+  auto to_stop = [&](int k) {
+    int64_t s = left[k];
+    const int every = args[k].obs_every;
+    if (every > 0) s = std::min<int64_t>(s, every - ctxs[k]->step % every);
+    return (int)s;
+  };
+  for (;;) {
+    std::vector<int> members;
+    int pairs = 0;
+    for (int k = 0; k < n; ++k)
+      if (to_stop(k) >= 2) {
+        members.push_back(k);
+        pairs = pairs == 0 ? to_stop(k) / 2 : std::min(pairs, to_stop(k) / 2);
+      }
+    if (!members.empty()) {
+      std::vector<int> key;
+      for (int k : members) {
+        key.push_back(k);
+        key.push_back(ctxs[k]->cur);
+      }
+      if (!g.exec || key != g.key) {
+        mfq_status st = capture_group(g, members);
+        if (st) return st;
+      }
+      hipStream_t origin = g.side[n];
+      for (int k : members) {  // the graph after the work queued on the members' streams
+        mfq_ctx *ck = ctxs[k];
+        HIPCHK(set_step(ck->step_dev, ck->step, false, ck->stream), "step counter");
+        HIPCHK(hipEventRecord(ready[k], ck->stream), "event record");
+        HIPCHK(hipStreamWaitEvent(origin, ready[k], 0), "stream wait");
+      }
+      for (int q = 0; q < pairs; ++q) HIPCHK(hipGraphLaunch(g.exec, origin), "group graph launch");
+      HIPCHK(hipEventRecord(g.event(n + 1), origin), "event record");
+      for (int k : members) {  // and the members' later work after it
+        HIPCHK(hipStreamWaitEvent(ctxs[k]->stream, g.event(n + 1), 0), "stream wait");
+        ctxs[k]->step += 2 * pairs;
+        left[k] -= 2 * pairs;
+      }
+    }
+    // contexts one step from their stop take it on their own stream; every context that moved
+    // observes when it reached a multiple of its obs_every (its pairs never pass one)
+    bool any = false;
+    for (int k = 0; k < n; ++k) {
+      mfq_ctx *ck = ctxs[k];
+      bool moved = std::find(members.begin(), members.end(), k) != members.end();
+      if (!moved && left[k] > 0) {
+        TileScope tiles(ck);
+        HIPCHK(set_step(ck->step_dev, ck->step, false, ck->stream), "step counter");
+        mfq_status st = enqueue_step(ck, args[k].protocol, args[k].dt, args[k].seed, 1);
+        if (st) return st;
+        ++ck->step;
+        --left[k];
+        moved = true;
+      }
+      const int every = args[k].obs_every;
+      if (moved && every > 0 && ck->step % every == 0) {
+        if (k_obs[k] >= args[k].n_obs) return fail(ck, MFQ_EDEVICE, "observation schedule");
+        TileScope tiles(ck);
+        mfq_status st = entropy_dev(ck, args[k].region, args[k].n_sites, args[k].S_host + (size_t)k_obs[k] * ck->B);
+        if (st) return st;
+        ++k_obs[k];
+      }
+      any = any || left[k] > 0;
+    }
+    if (!any) break;
+  }
+  for (int k = 0; k < n; ++k) {
+    mfq_ctx *ck = ctxs[k];
+    const hipError_t se = hipStreamSynchronize(ck->stream);
+    if (se != hipSuccess) return hip_fail(ck, se, "synchronize");
+  }
+  mfq_status worst = MFQ_OK;
+  for (int k = 0; k < n; ++k) {
+    const mfq_status st = check_flag(ctxs[k]);
+    if (st && !worst) worst = st;
+  }
+  return worst;
+}
+
 }  // namespace
 
 extern "C" {
@@ -907,6 +1092,7 @@ mfq_status mfq_set_integrator(mfq_ctx *c, int32_t integrator) {
 mfq_status mfq_run_group(mfq_ctx *const *ctxs, mfq_run_args *args, int32_t n) {
   if (!ctxs || !args || n < 1) return MFQ_EINVAL;
   if (n > FUSED_GROUP_MAX) return fail(ctxs[0], MFQ_EINVAL, "too many contexts for one launch");
+  bool all_fused = true;
   for (int k = 0; k < n; ++k) {
     mfq_ctx *c = ctxs[k];
     if (!c) return MFQ_EINVAL;
@@ -919,13 +1105,21 @@ mfq_status mfq_run_group(mfq_ctx *const *ctxs, mfq_run_args *args, int32_t n) {
     if (r.obs_every < 0) return fail(c, MFQ_EINVAL, "obs_every < 0");
     if (r.obs_every > 0 && (st = validate_region(c, r.region, r.n_sites))) return st;
     const int Ly = c->lat.dim == 2 ? c->lat.Ly : 1;
-    if (!fused_fits(c->L, c->N, c->lat.Lx, Ly))
-      return fail(c, MFQ_EINVAL, "problem does not fit the fused path (LDS)");
-    if (r.protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4)
-      return fail(c, MFQ_EINVAL, "the fused path integrates by split step only");
+    if (!fused_fits(c->L, c->N, c->lat.Lx, Ly) || (r.protocol == MFQ_HOMODYNE && c->integrator == MFQ_INTEGRATOR_RK4))
+      all_fused = false;
     const int n_obs = r.obs_every > 0 ? (int)((c->step + r.n_steps) / r.obs_every - c->step / r.obs_every) : 0;
     if (n_obs > 0 && !r.S_host) return fail(c, MFQ_EINVAL, "S_host is NULL");
     args[k].n_obs = n_obs;
+  }
+  if (!all_fused) {
+    for (int k = 0; k < n; ++k) {
+      mfq_ctx *c = ctxs[k];
+      if (args[k].protocol == MFQ_PROJECTIVE && blocked_pm(c))
+        return fail(c, MFQ_EINVAL, "blocked projective steps synchronise and cannot join a group graph");
+      if (!c->use_graphs || c->profiling)
+        return fail(c, MFQ_EINVAL, "graphs are disabled or profiling is on for this context");
+    }
+    return run_group_graph(ctxs, args, n);
   }
   mfq_ctx *c0 = ctxs[0];
   FusedGroup grp{};

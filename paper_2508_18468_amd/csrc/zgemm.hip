@@ -238,6 +238,18 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
 
   double ra_re[LA], ra_im[LA], rb_re[LB], rb_im[LB];
 
+  // Gathered rows that stay fixed over the K loop, read once: with op(A) = A every element of
+  // this thread lies in tile row a_fast, with op(B) = B^+ in tile column b_fast.
+  long a_row = 0, b_row = 0;
+  if constexpr (OPA == OP_N) {
+    const int gm = m0 + a_fast;
+    a_row = (GATHER && idxA) ? (gm < g.M ? idxA[gm] : 0) : gm;
+  }
+  if constexpr (OPB == OP_C) {
+    const int gn = n0 + b_fast;
+    b_row = (GATHER && idxB) ? (gn < g.N ? idxB[gn] : 0) : gn;
+  }
+
   auto load = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
@@ -251,8 +263,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
       if ((!EDGE || (gm < g.M && gk < kend)) && !zero) {
         cplx v;
         if (OPA == OP_N) {
-          const long row = idxA ? idxA[gm] : gm;
-          v = A[row + (long)gk * g.lda];
+          v = A[a_row + (long)gk * g.lda];
         } else {
           const long row = idxA ? idxA[gk] : gk;
           v = A[row + (long)gm * g.lda];
@@ -274,8 +285,7 @@ __device__ __forceinline__ void zgemm_body(const GemmDesc &g) {
           const long row = idxB ? idxB[gk] : gk;
           v = B[row + (long)gn * g.ldb];
         } else {
-          const long row = idxB ? idxB[gn] : gn;
-          v = B[row + (long)gk * g.ldb];
+          v = B[b_row + (long)gk * g.ldb];
           v.im = -v.im;
         }
         re = v.re; im = v.im;

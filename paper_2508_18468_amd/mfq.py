@@ -329,9 +329,10 @@ def mfq_run(ctx, protocol, gamma, dt, seed, n_steps, obs_every, region, n_traj, 
 
 
 def mfq_run_group(sims, specs):
-    """One fused launch for several Trajectories objects (mfq_run_group).  specs[k]: dict with
-    protocol, gamma, dt, seed, n_steps and optionally obs_every, region.  Returns the list of
-    S arrays (n_obs x n_traj) per context."""
+    """Several Trajectories objects advanced together (mfq_run_group): one fused launch when all
+    fit the fused kernel, else one graph replayed for pairs of steps of all of them.  specs[k]:
+    dict with protocol, gamma, dt, seed, n_steps and optionally obs_every, region.  Returns the
+    list of S arrays (n_obs x n_traj) per context."""
     n = len(sims)
     ctxs = (ctypes.c_void_p * n)(*[s.ctx for s in sims])
     args = (RunArgs * n)()

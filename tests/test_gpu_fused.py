@@ -183,9 +183,10 @@ def test_group_launch_errors():
     big = make_sim(1, 1024, n_traj=1)
     with pytest.raises(Exception):
         mfq.mfq_run_group([sims[0], big], [members[0], dict(members[0], gamma=[0.5])])
-    sims[1].set_integrator(mfq.INTEGRATOR_RK4)
-    with pytest.raises(Exception):
-        mfq.mfq_run_group(sims[:2], members[:2])                          # RK4 is not fused
+    with pytest.raises(Exception):                                        # blocked projective form
+        mfq.mfq_run_group([sims[1], big], [members[1], dict(members[0], gamma=[0.5], region=None, obs_every=0)])
+    sims[1].set_integrator(mfq.INTEGRATOR_RK4)                            # RK4 is not fused: one graph
+    assert [S.shape for S in mfq.mfq_run_group(sims[:2], members[:2])] == [(4, 4), (5, 3)]
     many = [make_sim(1, 16, n_traj=1, uids=[k]) for k in range(9)]
     spec = dict(protocol=PM, gamma=[0.5], dt=0.05, seed=0, n_steps=1)
     with pytest.raises(Exception):
@@ -193,3 +194,91 @@ def test_group_launch_errors():
     assert len(mfq.mfq_run_group(many[:8], [spec] * 8)) == 8
     for s in sims + many + [big]:
         s.close()
+
+
+def _graph_members():
+    """Lattices that do not fit the fused kernel: ring 160 homodyne (split step), ring 200 with
+    100 particles projective (per-workgroup measurement, N < 128), torus 12 x 12 homodyne by the
+    paper's RK4, ring 96 homodyne; uneven step counts and observation schedules."""
+    return [
+        dict(dim=1, Lx=160, Ly=1, uids=[1, 2, 3], protocol=QSD, gamma=[0.5, 1.0, 2.0], dt=0.05, seed=4,
+             n_steps=11, obs_every=4, region=list(range(80)), rk4=False),
+        dict(dim=1, Lx=200, Ly=1, uids=[4, 5], protocol=PM, gamma=[0.3, 1.0], dt=0.05, seed=5,
+             n_steps=7, obs_every=3, region=list(range(0, 200, 2)), rk4=False),
+        dict(dim=2, Lx=12, Ly=12, uids=[6, 7], protocol=QSD, gamma=[1.0, 0.4], dt=0.04, seed=6,
+             n_steps=10, obs_every=0, region=None, rk4=True),
+        dict(dim=1, Lx=96, Ly=1, uids=[8], protocol=QSD, gamma=[1.5], dt=0.05, seed=7,
+             n_steps=9, obs_every=2, region=list(range(48)), rk4=False),
+    ]
+
+
+def _graph_sim(m):
+    from paper_2508_18468_amd import mfq
+    sim = make_sim(m["dim"], m["Lx"], m["Ly"], n_traj=len(m["uids"]), uids=m["uids"])
+    sim.set_path(mfq.PATH_LAUNCHES)
+    if m["rk4"]:
+        sim.set_integrator(mfq.INTEGRATOR_RK4)
+    sim.step(QSD, [0.4] * sim.n_traj, 0.05, 9, 3)   # an odd prefix: the group starts at odd steps
+    return sim
+
+
+def test_group_graph_equals_separate_runs_and_oracle():
+    """Lattices above the fused kernel's size advance in one graph (two steps of each per
+    replay, parallel branches): observations and states equal each lattice run alone (bitwise:
+    same kernels, same draws), and the split-step ring follows the oracle (|dS| <= 1e-9)."""
+    from paper_2508_18468_amd import mfq
+    members = _graph_members()
+    grouped = [_graph_sim(m) for m in members]
+    S_grp = mfq.mfq_run_group(grouped, members)
+    for m, sim, S in zip(members, grouped, S_grp):
+        alone = _graph_sim(m)
+        S_alone = alone.run(m["protocol"], m["gamma"], m["dt"], m["seed"], m["n_steps"], m["obs_every"],
+                            m["region"])
+        assert S.shape == S_alone.shape and np.array_equal(S, S_alone), m["Lx"]
+        assert np.array_equal(sim.get_state()[0], alone.get_state()[0]), m["Lx"]
+        assert sim.step_index() == 3 + m["n_steps"]
+        alone.close()
+    m = members[0]
+    ob = OracleBatch(1, m["Lx"], 1, 0.05, m["uids"])
+    for _ in range(3):
+        ob.step(QSD, [0.4] * 3, 9)
+    k = 0
+    for n in range(4, 4 + m["n_steps"]):
+        ob.step(QSD, m["gamma"], m["seed"])
+        if n % m["obs_every"] == 0:
+            assert np.abs(S_grp[0][k] - ob.entropy(m["region"])).max() <= 1e-9
+            k += 1
+    assert k == S_grp[0].shape[0] == 3
+    for sim in grouped:
+        sim.close()
+
+
+def test_group_graph_timing():
+    """Four lattices above the fused kernel's size, 40 homodyne steps each: one group graph
+    against the lattices run one after another (printed; both paths give the same states)."""
+    from paper_2508_18468_amd import mfq
+    specs = [(1, 256, 1, 8), (1, 384, 1, 4), (2, 16, 16, 4), (1, 512, 1, 2)]
+    times = {}
+    states = {}
+    for mode in ("alone", "group", "alone", "group"):
+        sims = [make_sim(d, Lx, Ly, n_traj=b, uids=list(range(b))) for d, Lx, Ly, b in specs]
+        members = [dict(protocol=QSD, gamma=[1.0] * s.n_traj, dt=0.05, seed=3, n_steps=40) for s in sims]
+        for s in sims:
+            s.set_path(mfq.PATH_LAUNCHES)
+            s.step(QSD, [1.0] * s.n_traj, 0.05, 3, 2)
+            s.synchronize()
+        t0 = time.perf_counter()
+        if mode == "group":
+            mfq.mfq_run_group(sims, members)
+        else:
+            for s, sp in zip(sims, members):
+                s.run(QSD, sp["gamma"], 0.05, 3, 40)
+        for s in sims:
+            s.synchronize()
+        times[mode] = time.perf_counter() - t0
+        states[mode] = [s.get_state()[0] for s in sims]
+        for s in sims:
+            s.close()
+    for a, b in zip(states["alone"], states["group"]):
+        assert np.array_equal(a, b)
+    print(f"group graph: {times['group'] * 1e3:.1f} ms; one after another: {times['alone'] * 1e3:.1f} ms")
