@@ -23,8 +23,9 @@
 // reflectors, only the lower triangle of the trailing matrix read per reflector,
 // the matrix written once per panel by a GEMM): about a quarter of that traffic.
 // Bisection: one lane per eigenvalue when the batch offers enough of them,
-// otherwise one wave per eigenvalue that splits its interval at 64 points per
-// Sturm pass (65-fold narrowing per pass instead of 2-fold).
+// otherwise P lanes per eigenvalue that split its interval at P points per Sturm
+// pass ((P + 1)-fold narrowing per pass instead of 2-fold), P as large as keeps
+// the batch within about four waves per SIMD.
 #include <algorithm>
 
 #include "device_common.h"
@@ -34,8 +35,10 @@ namespace mfq {
 namespace {
 
 constexpr int LDS_MAX_N = 88;  // 88 * 88 * 16 B = 121 KiB
-// below this many eigenvalues in a batch, one wave per eigenvalue (multisection)
+// below this many eigenvalues in a batch, multisection with P lanes per eigenvalue, P the
+// largest power of two up to 64 that keeps n B P within BISECT_MULTI_LANES
 constexpr long BISECT_LANES_MIN = 131072;
+constexpr long BISECT_MULTI_LANES = 262144;
 
 __global__ __launch_bounds__(256) void tridiag_lds_kernel(EigWork w, int n) {
   const int b = blockIdx.x;
@@ -654,15 +657,17 @@ __global__ __launch_bounds__(256) void bisect_kernel(EigWork w, int n) {
   w.lam[(long)b * n + k] = bisect_eigenvalue(w.d + (long)b * n, w.e + (long)b * n, n, k);
 }
 
-// Eigenvalue blockIdx.x * 4 + wave of tridiagonal blockIdx.y by multisection:
-// the 64 lanes evaluate the Sturm count at 64 interior points of the current
-// interval, which shrinks to the gap between the last point below lambda_k
-// and the first above it.  Same interval, pivmin and stopping width as
-// bisect_eigenvalue.
-__global__ __launch_bounds__(256) void bisect_multi_kernel(EigWork w, int n) {
+// Eigenvalues of tridiagonal blockIdx.y by multisection with P lanes per eigenvalue (P a power
+// of two, 2 <= P <= 64; 64 / P eigenvalues per wave, eigenvalue k = (blockIdx.x * 4 + wave) *
+// (64 / P) + lane / P): the P lanes of an eigenvalue evaluate the Sturm count at P interior
+// points of its interval, which shrinks to the gap between the last point below lambda_k and
+// the first above it.  Same interval, pivmin and stopping width as bisect_eigenvalue.
+__global__ __launch_bounds__(256) void bisect_multi_kernel(EigWork w, int n, int P) {
   const int b = blockIdx.y, lane = threadIdx.x & 63;
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (k >= n) return;
+  const int G = 64 / P, grp = lane / P, pl = lane % P;
+  const int k0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * G;
+  if (k0 >= n) return;  // uniform over the wave
+  const int k = k0 + grp;
   const double *d = w.d + (long)b * n, *e = w.e + (long)b * n;
   double lo = d[0], hi = d[0], emax2 = 0.0;
   for (int i = lane; i < n; i += 64) {
@@ -681,17 +686,24 @@ __global__ __launch_bounds__(256) void bisect_multi_kernel(EigWork w, int n) {
   lo -= 2.0 * 2.220446049250313e-16 * span + 2.0 * pivmin;
   hi += 2.0 * 2.220446049250313e-16 * span + 2.0 * pivmin;
   const double tol = 4.0 * 2.220446049250313e-16 * fmax(1.0, span);
-  for (int it = 0; it < 40 && hi - lo > tol; ++it) {
-    const double x = lo + (hi - lo) * ((double)(lane + 1) / 65.0);
-    const bool above = sturm_count(d, e, n, x, pivmin) > k;
-    const unsigned long long m = __ballot(above);
-    const int first = m ? __ffsll((long long)m) - 1 : 64;
-    const double nhi = __shfl(x, first < 64 ? first : 0, 64);
-    const double nlo = __shfl(x, first > 0 ? first - 1 : 0, 64);
-    if (first < 64) hi = nhi;
-    if (first > 0) lo = nlo;
+  // each pass divides the interval by P + 1; 60 halvings cover any start width over tol
+  const int max_it = (int)(60.0 / log2((double)(P + 1))) + 4;
+  const unsigned long long gmask = (P == 64 ? ~0ull : ((1ull << P) - 1)) << (grp * P);
+  for (int it = 0; it < max_it; ++it) {
+    const bool open = k < n && hi - lo > tol;  // uniform over the eigenvalue's lanes
+    if (__ballot(open) == 0) break;
+    const double x = lo + (hi - lo) * ((double)(pl + 1) / (double)(P + 1));
+    const bool above = open && sturm_count(d, e, n, x, pivmin) > k;
+    const unsigned long long m = __ballot(above) & gmask;
+    const int first = m ? __ffsll((long long)m) - 1 - grp * P : P;  // first point above, in the group
+    const double nhi = __shfl(x, grp * P + (first < P ? first : 0), 64);
+    const double nlo = __shfl(x, grp * P + (first > 0 ? first - 1 : 0), 64);
+    if (open) {
+      if (first < P) hi = nhi;
+      if (first > 0) lo = nlo;
+    }
   }
-  if (lane == 0) w.lam[(long)b * n + k] = bracket_estimate(lo, hi);
+  if (k < n && pl == 0) w.lam[(long)b * n + k] = bracket_estimate(lo, hi);
 }
 
 // S = sum_k h(lambda_k), h(x) = -x ln x - (1 - x) ln(1 - x), lambda clamped to [0, 1].
@@ -865,10 +877,15 @@ hipError_t tridiagonalize(const EigWork &w, int n, int B, hipStream_t s) {
 }
 
 hipError_t bisect_eigvals(const EigWork &w, int n, int B, hipStream_t s) {
-  if ((long)n * B >= BISECT_LANES_MIN)
+  const long nb = (long)n * B;
+  if (nb >= BISECT_LANES_MIN) {
     hipLaunchKernelGGL(bisect_kernel, dim3((n + 255) / 256, B), dim3(256), 0, s, w, n);
-  else
-    hipLaunchKernelGGL(bisect_multi_kernel, dim3((n + 3) / 4, B), dim3(256), 0, s, w, n);
+  } else {
+    int P = 64;
+    while (P > 2 && nb * P > BISECT_MULTI_LANES) P /= 2;
+    const int per_wg = 4 * (64 / P);
+    hipLaunchKernelGGL(bisect_multi_kernel, dim3((n + per_wg - 1) / per_wg, B), dim3(256), 0, s, w, n, P);
+  }
   return hipGetLastError();
 }
 
