@@ -25,7 +25,7 @@
 // Bisection: one lane per eigenvalue when the batch offers enough of them,
 // otherwise P lanes per eigenvalue that split its interval at P points per Sturm
 // pass ((P + 1)-fold narrowing per pass instead of 2-fold), P as large as keeps
-// the batch within about four waves per SIMD.
+// the batch within about two waves per SIMD.
 #include <algorithm>
 
 #include "device_common.h"
@@ -36,9 +36,10 @@ namespace {
 
 constexpr int LDS_MAX_N = 88;  // 88 * 88 * 16 B = 121 KiB
 // below this many eigenvalues in a batch, multisection with P lanes per eigenvalue, P the
-// largest power of two up to 64 that keeps n B P within BISECT_MULTI_LANES
+// largest power of two up to 64 that keeps n B P within BISECT_MULTI_LANES (two waves per
+// SIMD; two 8192-site spectra: P = 8 18.6 ms, 16 22.9 ms, 32 33.4 ms, 64 54 ms)
 constexpr long BISECT_LANES_MIN = 131072;
-constexpr long BISECT_MULTI_LANES = 262144;
+constexpr long BISECT_MULTI_LANES = 131072;
 
 __global__ __launch_bounds__(256) void tridiag_lds_kernel(EigWork w, int n) {
   const int b = blockIdx.x;
