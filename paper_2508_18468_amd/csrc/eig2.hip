@@ -33,7 +33,12 @@
 // Reflectors are Hermitian, H = I - tau v v^+ with real tau (make_reflector), formed from the
 // vector scaled by its largest component.  The final tridiagonal has complex sub-diagonal
 // entries; a diagonal unitary similarity makes them |e_i| without changing the spectrum.
+#include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "device_common.h"
 
@@ -299,7 +304,8 @@ __global__ __launch_bounds__(256) void p1_col_kernel(EigWork W, int n, int j, in
 // per-matrix counter that started the panel at `base` (the statistics that column k reduces
 // are then complete, and the buffer that column k overwrites is no longer read).  Workgroups
 // therefore depend on workgroups that may not have started: the host launches this kernel only
-// when the grid fits the GPU at once.  A wait longer than `limit` wall-clock ticks sets the abort
+// when its grid, with those of the panel kernels of other streams that may run beside it, fits
+// the GPU at once (launch_panel).  A wait longer than `limit` wall-clock ticks sets the abort
 // word and the context's error flag, and every workgroup leaves.
 __global__ __launch_bounds__(256) void p1_panel_kernel(EigWork W, int n, int j, int m, int kmax, int g1, int gm,
                                                        int base, long long limit) {
@@ -685,6 +691,58 @@ long panel_capacity() {
   return c > 0 ? c : 0;
 }
 
+// Panel kernels that may run at once on one device.  The workgroups of a panel kernel wait for
+// each other, so the panel kernels that can run together must fit the GPU together: the latest
+// panel kernel of each stream is recorded (its stream runs the earlier ones before it), and a
+// new one first makes its stream wait, on the GPU, for the earliest recorded ones of other
+// streams until its grid and theirs fit.  Waits point only at kernels enqueued earlier, so they
+// form no cycle.
+struct PanelSlot {
+  hipEvent_t ev = nullptr;
+  long wgs = 0;  // 0: finished
+  long seq = 0;
+};
+std::mutex g_panel_mu;
+std::map<std::pair<int, hipStream_t>, PanelSlot> g_panel_slots;
+long g_panel_seq = 0;
+
+hipError_t launch_panel(const EigWork &w, int n, int j, int m, int kmax, int g1, int gm, int B, int base,
+                        long long wait_ticks, long cap, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const long wgs = (long)gm * B;
+  std::lock_guard<std::mutex> lock(g_panel_mu);
+  std::vector<PanelSlot *> others;
+  long sum = wgs;
+  for (auto &kv : g_panel_slots) {
+    PanelSlot &p = kv.second;
+    if (kv.first.first != dev || kv.first.second == s || p.wgs == 0) continue;
+    const hipError_t q = hipEventQuery(p.ev);
+    if (q == hipSuccess) {
+      p.wgs = 0;
+      continue;
+    }
+    if (q != hipErrorNotReady) return q;
+    sum += p.wgs;
+    others.push_back(&p);
+  }
+  std::sort(others.begin(), others.end(), [](const PanelSlot *a, const PanelSlot *b) { return a->seq < b->seq; });
+  for (PanelSlot *p : others) {
+    if (sum <= cap) break;
+    if ((e = hipStreamWaitEvent(s, p->ev, 0)) != hipSuccess) return e;
+    sum -= p->wgs;
+  }
+  hipLaunchKernelGGL(p1_panel_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, kmax, g1, gm, base, wait_ticks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  PanelSlot &mine = g_panel_slots[{dev, s}];
+  if (!mine.ev && (e = hipEventCreateWithFlags(&mine.ev, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventRecord(mine.ev, s)) != hipSuccess) return e;
+  mine.wgs = wgs;
+  mine.seq = ++g_panel_seq;
+  return hipSuccess;
+}
+
 // K slices for a product with `tiles` output tiles per matrix and depth K: at most `ksmax`, at
 // most `wgs` workgroups in all, slices at least `depth` deep.
 int kslices(long tiles, int K, int B, long wgs, int depth, int ksmax) {
@@ -729,10 +787,8 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
   for (int j = 0; n - j - SB >= 2; j += SB) {
     const int m = n - j - SB, kmax = std::min(m, SB), gm = (m + P1_RPW - 1) / P1_RPW;
     cplx *A22 = w.A + (j + SB) + (long)(j + SB) * n;
-    if ((long)gm * B <= cap / 2) {  // half of what the GPU holds at once: room for other streams
-      hipLaunchKernelGGL(p1_panel_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, kmax, g1, gm, base,
-                         wait_ticks);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((long)gm * B <= cap * 3 / 4) {  // a quarter of the GPU left to other work
+      if ((e = launch_panel(w, n, j, m, kmax, g1, gm, B, base, wait_ticks, cap, s)) != hipSuccess) return e;
       base += gm * (kmax + 1);
     } else {
       for (int k = -1; k < kmax; ++k) {

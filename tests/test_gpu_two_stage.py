@@ -104,3 +104,62 @@ def test_two_stage_trajectories_against_oracle():
                     assert np.abs(spec[path][t] - want).max() <= 1e-11, (protocol, len(region), path)
                 assert np.abs(spec[ONE][t] - spec[TWO][t]).max() <= 1e-11
         sim.close()
+
+
+def test_two_stage_panel_forms_agree():
+    """Sixteen trajectories of a 6400-site ring, region of 3200 sites: the first panels' grid
+    (25 workgroups per matrix, 400 in all) exceeds three quarters of what the GPU holds at once,
+    so they run as one launch per column, and the later panels (24 per matrix) run in the panel
+    kernel; the spectra match the one-stage reduction (1e-11) after a few homodyne steps."""
+    L, B = 6400, 16
+    sim = make_sim(1, L, n_traj=B, uids=list(range(B)))
+    sim.step(1, [0.5 + 0.1 * t for t in range(B)], 0.05, 3, 2)
+    region = list(range(3200))
+    spec = {}
+    for path in (ONE, TWO):
+        sim.set_eig_path(path)
+        print(f"panel forms: eig path {path}", flush=True)
+        spec[path] = np.sort(sim.region_spectrum(region), axis=1)
+    assert np.abs(spec[ONE] - spec[TWO]).max() <= 1e-11
+    assert np.all(spec[TWO] > -1e-12) and np.all(spec[TWO] < 1.0 + 1e-12)
+    sim.close()
+
+
+def test_two_stage_panel_kernels_on_two_streams():
+    """Two contexts on two streams reduce 6400-site region Grams of six trajectories from two
+    host threads at once: 300 panel-kernel workgroups each, more than the GPU holds for both, so
+    a panel kernel of one stream waits on the GPU for the other's running one; both spectra
+    match the one-stage reduction (1e-11)."""
+    import threading
+    import torch
+    L, B = 12800, 6
+    sims = []
+    for k in range(2):
+        with torch.cuda.stream(torch.cuda.Stream()):
+            sims.append(make_sim(1, L, n_traj=B, uids=list(range(10 * k, 10 * k + B))))
+    region = list(range(6400))
+    ref = []
+    for sim in sims:
+        sim.step(1, [0.5] * B, 0.05, 3, 2)
+        sim.set_eig_path(ONE)
+        ref.append(np.sort(sim.region_spectrum(region), axis=1))
+        sim.set_eig_path(TWO)
+    print("panel kernels on two streams: one-stage references done", flush=True)
+    out, errs = [None, None], []
+
+    def work(k):
+        try:
+            out[k] = np.sort(sims[k].region_spectrum(region), axis=1)
+        except Exception as ex:  # reported below
+            errs.append(ex)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for k in range(2):
+        assert np.abs(out[k] - ref[k]).max() <= 1e-11
+    for sim in sims:
+        sim.close()
