@@ -2,6 +2,7 @@
 // drivers.  Every arithmetic step runs in the HIP kernels of this library;
 // the host only validates arguments, computes the propagator's generating
 // row (a Bessel series, once per dt) and orders launches on the stream.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -13,7 +14,7 @@
 #include <vector>
 
 #include "../../include/mfq.h"
-#include <algorithm>
+#include "group_schedule.h"
 
 #include "mfq_internal.h"
 
@@ -669,29 +670,22 @@ mfq_status run_group_graph(mfq_ctx *const *ctxs, const mfq_run_args *args, int n
     g.evs.push_back(ev);
     ready[k] = ev;
   }
-  std::vector<int> left(n), k_obs(n, 0);
+  std::vector<int64_t> left(n), now(n);
+  std::vector<int> every(n), k_obs(n, 0);
   for (int k = 0; k < n; ++k) {
     mfq_ctx *ck = ctxs[k];
     mfq_status st = prepare_step(ck, args[k].gamma, args[k].dt);
     if (!st && args[k].protocol == MFQ_HOMODYNE && ck->integrator == MFQ_INTEGRATOR_RK4) st = ensure_rk4(ck);
     if (st) return st;
     left[k] = args[k].n_steps;
+    every[k] = args[k].obs_every;
   }
-  // steps of context k before its next stop
-  auto to_stop = [&](int k) {
-    int64_t s = left[k];
-    const int every = args[k].obs_every;
-    if (every > 0) s = std::min<int64_t>(s, every - ctxs[k]->step % every);
-    return (int)s;
-  };
   for (;;) {
-    std::vector<int> members;
-    int pairs = 0;
-    for (int k = 0; k < n; ++k)
-      if (to_stop(k) >= 2) {
-        members.push_back(k);
-        pairs = pairs == 0 ? to_stop(k) / 2 : std::min(pairs, to_stop(k) / 2);
-      }
+    for (int k = 0; k < n; ++k) now[k] = ctxs[k]->step;
+    const mfq_group::Round round = mfq_group::plan_round(left, now, every);
+    if (round.members.empty() && round.singles.empty()) break;
+    const std::vector<int> &members = round.members;
+    const int64_t pairs = round.pairs;
     if (!members.empty()) {
       std::vector<int> key;
       for (int k : members) {
@@ -709,7 +703,7 @@ mfq_status run_group_graph(mfq_ctx *const *ctxs, const mfq_run_args *args, int n
         HIPCHK(hipEventRecord(ready[k], ck->stream), "event record");
         HIPCHK(hipStreamWaitEvent(origin, ready[k], 0), "stream wait");
       }
-      for (int q = 0; q < pairs; ++q) HIPCHK(hipGraphLaunch(g.exec, origin), "group graph launch");
+      for (int64_t q = 0; q < pairs; ++q) HIPCHK(hipGraphLaunch(g.exec, origin), "group graph launch");
       HIPCHK(hipEventRecord(g.event(n + 1), origin), "event record");
       for (int k : members) {  // and the members' later work after it
         HIPCHK(hipStreamWaitEvent(ctxs[k]->stream, g.event(n + 1), 0), "stream wait");
@@ -717,32 +711,30 @@ mfq_status run_group_graph(mfq_ctx *const *ctxs, const mfq_run_args *args, int n
         left[k] -= 2 * pairs;
       }
     }
-    // contexts one step from their stop take it on their own stream; every context that moved
-    // observes when it reached a multiple of its obs_every (its pairs never pass one)
-    bool any = false;
+    // contexts one step from their stop take it on their own stream
+    for (int k : round.singles) {
+      mfq_ctx *ck = ctxs[k];
+      TileScope tiles(ck);
+      HIPCHK(set_step(ck->step_dev, ck->step, false, ck->stream), "step counter");
+      mfq_status st = enqueue_step(ck, args[k].protocol, args[k].dt, args[k].seed, 1);
+      if (st) return st;
+      ++ck->step;
+      --left[k];
+    }
+    // every context that moved observes when it reached a multiple of its obs_every (the
+    // schedule never takes it past one)
     for (int k = 0; k < n; ++k) {
       mfq_ctx *ck = ctxs[k];
-      bool moved = std::find(members.begin(), members.end(), k) != members.end();
-      if (!moved && left[k] > 0) {
-        TileScope tiles(ck);
-        HIPCHK(set_step(ck->step_dev, ck->step, false, ck->stream), "step counter");
-        mfq_status st = enqueue_step(ck, args[k].protocol, args[k].dt, args[k].seed, 1);
-        if (st) return st;
-        ++ck->step;
-        --left[k];
-        moved = true;
-      }
-      const int every = args[k].obs_every;
-      if (moved && every > 0 && ck->step % every == 0) {
+      const bool moved = std::find(members.begin(), members.end(), k) != members.end() ||
+                         std::find(round.singles.begin(), round.singles.end(), k) != round.singles.end();
+      if (moved && every[k] > 0 && ck->step % every[k] == 0) {
         if (k_obs[k] >= args[k].n_obs) return fail(ck, MFQ_EDEVICE, "observation schedule");
         TileScope tiles(ck);
         mfq_status st = entropy_dev(ck, args[k].region, args[k].n_sites, args[k].S_host + (size_t)k_obs[k] * ck->B);
         if (st) return st;
         ++k_obs[k];
       }
-      any = any || left[k] > 0;
     }
-    if (!any) break;
   }
   for (int k = 0; k < n; ++k) {
     mfq_ctx *ck = ctxs[k];
