@@ -41,6 +41,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "panel_admission.h"
 
 namespace mfq {
 
@@ -691,16 +692,11 @@ long panel_capacity() {
   return c > 0 ? c : 0;
 }
 
-// Panel kernels that may run at once on one device.  The workgroups of a panel kernel wait for
-// each other, so the panel kernels that can run together must fit the GPU together: the latest
-// panel kernel of each stream is recorded (its stream runs the earlier ones before it), and a
-// new one first makes its stream wait, on the GPU, for the earliest recorded ones of other
-// streams until its grid and theirs fit.  Waits point only at kernels enqueued earlier, so they
-// form no cycle.
+// Panel kernels that may run at once on one device: the records of panel_admission.h, one per
+// (device, stream), each with the event recorded after that stream's latest panel kernel.
 struct PanelSlot {
   hipEvent_t ev = nullptr;
-  long wgs = 0;  // 0: finished
-  long seq = 0;
+  mfq_panel::Record rec;
 };
 std::mutex g_panel_mu;
 std::map<std::pair<int, hipStream_t>, PanelSlot> g_panel_slots;
@@ -713,33 +709,35 @@ hipError_t launch_panel(const EigWork &w, int n, int j, int m, int kmax, int g1,
   if (e != hipSuccess) return e;
   const long wgs = (long)gm * B;
   std::lock_guard<std::mutex> lock(g_panel_mu);
-  std::vector<PanelSlot *> others;
-  long sum = wgs;
+  std::vector<PanelSlot *> slots;
+  std::vector<mfq_panel::Record> others;
   for (auto &kv : g_panel_slots) {
     PanelSlot &p = kv.second;
-    if (kv.first.first != dev || kv.first.second == s || p.wgs == 0) continue;
+    if (kv.first.first != dev || kv.first.second == s || p.rec.wgs == 0) continue;
     const hipError_t q = hipEventQuery(p.ev);
     if (q == hipSuccess) {
-      p.wgs = 0;
+      p.rec.wgs = 0;
       continue;
     }
     if (q != hipErrorNotReady) return q;
-    sum += p.wgs;
-    others.push_back(&p);
+    slots.push_back(&p);
+    others.push_back(p.rec);
   }
-  std::sort(others.begin(), others.end(), [](const PanelSlot *a, const PanelSlot *b) { return a->seq < b->seq; });
-  for (PanelSlot *p : others) {
-    if (sum <= cap) break;
-    if ((e = hipStreamWaitEvent(s, p->ev, 0)) != hipSuccess) return e;
-    sum -= p->wgs;
+  for (int i : mfq_panel::waits_for(others, wgs, cap))
+    if ((e = hipStreamWaitEvent(s, slots[i]->ev, 0)) != hipSuccess) return e;
+  PanelSlot &mine = g_panel_slots[{dev, s}];
+  bool finished = true;
+  if (mine.ev && mine.rec.wgs > 0) {
+    const hipError_t q = hipEventQuery(mine.ev);
+    if (q != hipSuccess && q != hipErrorNotReady) return q;
+    finished = q == hipSuccess;
   }
   hipLaunchKernelGGL(p1_panel_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, kmax, g1, gm, base, wait_ticks);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  PanelSlot &mine = g_panel_slots[{dev, s}];
   if (!mine.ev && (e = hipEventCreateWithFlags(&mine.ev, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventRecord(mine.ev, s)) != hipSuccess) return e;
-  mine.wgs = wgs;
-  mine.seq = ++g_panel_seq;
+  mine.rec.wgs = mfq_panel::recorded_wgs(mine.rec.wgs, finished, wgs);
+  mine.rec.seq = ++g_panel_seq;
   return hipSuccess;
 }
 
