@@ -50,7 +50,6 @@ namespace {
 constexpr int SB = TRD2_SB;
 constexpr int PAYC = 2 + 2 * SB;  // complex entries of one workgroup's column statistics
 constexpr int P1_RPW = TRD2_RPW;  // panel rows per workgroup of the column launches
-constexpr int KS_MAX = TRD2_KS;   // K slices of the deep products
 
 // Per-matrix scratch inside EigWork::panel (complex units from the matrix's base).
 struct Scratch {
@@ -693,13 +692,17 @@ long panel_capacity() {
 }
 
 // Panel kernels that may run at once on one device: the records of panel_admission.h, one per
-// (device, stream), each with the event recorded after that stream's latest panel kernel.
+// (device, stream).  A record's event is recorded on a stream of the library's own, made to wait
+// for the panel kernel first: a context's stream may later be captured into a graph, after which
+// the runtime refuses queries of events last recorded on it, while the library's stream is never
+// captured.
 struct PanelSlot {
   hipEvent_t ev = nullptr;
   mfq_panel::Record rec;
 };
 std::mutex g_panel_mu;
 std::map<std::pair<int, hipStream_t>, PanelSlot> g_panel_slots;
+std::map<int, hipStream_t> g_panel_streams;
 long g_panel_seq = 0;
 
 hipError_t launch_panel(const EigWork &w, int n, int j, int m, int kmax, int g1, int gm, int B, int base,
@@ -709,6 +712,11 @@ hipError_t launch_panel(const EigWork &w, int n, int j, int m, int kmax, int g1,
   if (e != hipSuccess) return e;
   const long wgs = (long)gm * B;
   std::lock_guard<std::mutex> lock(g_panel_mu);
+  hipStream_t &own = g_panel_streams[dev];
+  if (!own && (e = hipStreamCreateWithFlags(&own, hipStreamNonBlocking)) != hipSuccess) {
+    own = nullptr;
+    return e;
+  }
   std::vector<PanelSlot *> slots;
   std::vector<mfq_panel::Record> others;
   for (auto &kv : g_panel_slots) {
@@ -725,44 +733,32 @@ hipError_t launch_panel(const EigWork &w, int n, int j, int m, int kmax, int g1,
   }
   for (int i : mfq_panel::waits_for(others, wgs, cap))
     if ((e = hipStreamWaitEvent(s, slots[i]->ev, 0)) != hipSuccess) return e;
+  // this stream's earlier panel kernels are not queried here: the bound keeps their grid until
+  // another stream finds the record finished
   PanelSlot &mine = g_panel_slots[{dev, s}];
-  bool finished = true;
-  if (mine.ev && mine.rec.wgs > 0) {
-    const hipError_t q = hipEventQuery(mine.ev);
-    if (q != hipSuccess && q != hipErrorNotReady) return q;
-    finished = q == hipSuccess;
-  }
+  const bool finished = mine.rec.wgs == 0;
   hipLaunchKernelGGL(p1_panel_kernel, dim3(gm, B), dim3(256), 0, s, w, n, j, m, kmax, g1, gm, base, wait_ticks);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the record's event: on the library's stream, after the panel kernel
+  hipEvent_t after = nullptr;
+  if ((e = hipEventCreateWithFlags(&after, hipEventDisableTiming)) != hipSuccess) return e;
+  e = hipEventRecord(after, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(own, after, 0);
+  (void)hipEventDestroy(after);
+  if (e != hipSuccess) return e;
   if (!mine.ev && (e = hipEventCreateWithFlags(&mine.ev, hipEventDisableTiming)) != hipSuccess) return e;
-  if ((e = hipEventRecord(mine.ev, s)) != hipSuccess) return e;
+  if ((e = hipEventRecord(mine.ev, own)) != hipSuccess) return e;
   mine.rec.wgs = mfq_panel::recorded_wgs(mine.rec.wgs, finished, wgs);
   mine.rec.seq = ++g_panel_seq;
   return hipSuccess;
 }
 
-// K slices for a product with `tiles` output tiles per matrix and depth K: at most `ksmax`, at
-// most `wgs` workgroups in all, slices at least `depth` deep.
-int kslices(long tiles, int K, int B, long wgs, int depth, int ksmax) {
-  int ks = 1;
-  while (ks * 2 <= ksmax && tiles * B * ks * 2 <= wgs && K / (2 * ks) >= depth) ks *= 2;
-  return ks;
-}
-
-// Slices of depth K that ksplit forms when asked for ks: their depth kc (whole K chunks when
-// split), and their number (every slice non-empty).
-int slice_depth(int K, int ks) {
-  const int kc = (K + ks - 1) / ks;
-  return ks > 1 ? (kc + 15) / 16 * 16 : kc;
-}
-int slice_count(int K, int ks) { return (K + slice_depth(K, ks) - 1) / slice_depth(K, ks); }
-
-// g (depth K) split over K in one launch into slice_count(K, ks) slices: slice q covers K
-// indices [q kc, min((q + 1) kc, K)), kc = slice_depth(K, ks), its partial into D + q sDq.
+// g (depth K) split over K in one launch into trd2_slice_count(K, ks) slices: slice q covers K
+// indices [q kc, min((q + 1) kc, K)), kc = trd2_slice_depth(K, ks), its partial into D + q sDq.
 // dA, dB: operand offsets per unit of K.  The slices' partials are summed by p1_ksum_kernel.
 hipError_t ksplit(GemmDesc g, int B, int K, int ks, long dA, long dB, long sDq, hipStream_t s) {
-  const int kc = slice_depth(K, ks);
-  ks = slice_count(K, ks);
+  const int kc = trd2_slice_depth(K, ks);
+  ks = trd2_slice_count(K, ks);
   g.K = kc; g.batch = B * ks; g.batch2 = ks;
   g.sA2 = kc * dA; g.sB2 = kc * dB; g.sD2 = sDq;
   g.kofs = 0; g.kofs2 = kc; g.kend_glob = K;
@@ -795,7 +791,7 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
       }
     }
     {  // S = V^+ V
-      const int ks = slice_count(m, kslices(1, m, B, 512, 64, trd2_ks_max(n)));
+      const int ks = trd2_sb_slices(n, m, B);
       if ((long)ks * SB * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;
@@ -819,9 +815,7 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
     }
     {  // X = A22 (V T) from the lower triangle of A22: tril(A22) (V T) + striu(A22^+) (V T),
        // each split over K, all partials summed into the W columns of X
-      int ks = kslices((m + 63) / 64, m, B, 4096, 128, KS_MAX);
-      while (ks > 1 && 2L * ks * m * SB > trd2_kp_elems(n)) ks /= 2;
-      ks = slice_count(m, ks);
+      const int ks = trd2_x_slices(n, m, B);
       if (2L * ks * m * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = m; g.N = SB; g.batch = B;
@@ -837,7 +831,7 @@ hipError_t tridiagonalize_two_stage(const EigWork &w, int n, int B, long long wa
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {  // Z = V^+ X
-      const int ks = slice_count(m, kslices(1, m, B, 512, 64, trd2_ks_max(n)));
+      const int ks = trd2_sb_slices(n, m, B);
       if ((long)ks * SB * SB > trd2_kp_elems(n)) return hipErrorInvalidValue;
       GemmDesc g = gdesc();
       g.M = SB; g.N = SB; g.batch = B;

@@ -58,9 +58,38 @@ MFQ_LAYOUT_HD inline long trd2_kp_elems(int n) {
   const long ab = a > b ? a : b;
   return ab > c ? ab : c;
 }
+// K splits of the band reduction's deep products (eig2.hip).  kslices: the largest power of two
+// up to ksmax with at most `wgs` workgroups in all (`tiles` output tiles per matrix, B matrices)
+// and slices at least `depth` deep.  A split of depth K asked for ks slices forms slices of
+// trd2_slice_depth(K, ks) (whole K chunks of 16 when split), trd2_slice_count(K, ks) of them,
+// every one non-empty.
+MFQ_LAYOUT_HD inline int trd2_kslices(long tiles, int K, int B, long wgs, int depth, int ksmax) {
+  int ks = 1;
+  while (ks * 2 <= ksmax && tiles * B * ks * 2 <= wgs && K / (2 * ks) >= depth) ks *= 2;
+  return ks;
+}
+MFQ_LAYOUT_HD inline int trd2_slice_depth(int K, int ks) {
+  const int kc = (K + ks - 1) / ks;
+  return ks > 1 ? (kc + 15) / 16 * 16 : kc;
+}
+MFQ_LAYOUT_HD inline int trd2_slice_count(int K, int ks) {
+  return (K + trd2_slice_depth(K, ks) - 1) / trd2_slice_depth(K, ks);
+}
 MFQ_LAYOUT_HD inline long trd2_scratch_elems(int n) {
   return (long)n * 5 * TRD2_SB + trd2_kp_elems(n) + 4L * TRD2_SB * TRD2_SB + TRD2_SB +
          (long)trd2_groups(n) * 2 * (2 + 2 * TRD2_SB) + (n + 64 + 3) / 4;
+}
+
+// Slices of the panel products of order n with m rows below the band and B matrices: the two
+// halves of X = A22 (V T) (m x TRD2_SB each, both sets of partials within trd2_kp_elems) and the
+// TRD2_SB x TRD2_SB products V^+ V and V^+ X.
+MFQ_LAYOUT_HD inline int trd2_x_slices(int n, int m, int B) {
+  int ks = trd2_kslices((m + 63) / 64, m, B, 4096, 128, TRD2_KS);
+  while (ks > 1 && 2L * ks * m * TRD2_SB > trd2_kp_elems(n)) ks /= 2;
+  return trd2_slice_count(m, ks);
+}
+MFQ_LAYOUT_HD inline int trd2_sb_slices(int n, int m, int B) {
+  return trd2_slice_count(m, trd2_kslices(1, m, B, 512, 64, trd2_ks_max(n)));
 }
 
 // Bessel-recurrence scratch length per trajectory (continuous-time protocol) for rings up to
