@@ -693,9 +693,9 @@ long panel_capacity() {
 
 // Panel kernels that may run at once on one device: the records of panel_admission.h, one per
 // (device, stream).  A record's event is recorded on a stream of the library's own, made to wait
-// for the panel kernel first: a context's stream may later be captured into a graph, after which
-// the runtime refuses queries of events last recorded on it, while the library's stream is never
-// captured.
+// for the panel kernel first: a query of an event last recorded on a context's stream has failed
+// (hipErrorCapturedEvent) once that stream had been captured into its step-pair graphs, while the
+// library's stream is never captured.
 struct PanelSlot {
   hipEvent_t ev = nullptr;
   mfq_panel::Record rec;
