@@ -110,6 +110,25 @@ int main() {
     CHECK(trd2_kp_elems(n) >= 2L * TRD2_SB * (n - TRD2_SB));
     CHECK(trd2_kp_elems(n) >= (long)trd2_ks_max(n) * TRD2_SB * TRD2_SB);
   }
+  // the panel products' K splits as the reduction forms them: slices non-empty, whole K chunks
+  // when split, and both halves of X (and the 32 x 32 products) within the partial storage
+  name = "two-stage K splits";
+  const int batches[] = {1, 2, 3, 16, 384};
+  for (int n = 2 * TRD2_SB + 2; n <= 20000; n += (n < 1024 ? 7 : 331))
+    for (int B : batches)
+      for (int j = 0; n - j - TRD2_SB >= 2; j += TRD2_SB) {
+        const int m = n - j - TRD2_SB;
+        const int kx = trd2_x_slices(n, m, B), ks = trd2_sb_slices(n, m, B);
+        for (int q : {kx, ks}) {
+          const int kc = trd2_slice_depth(m, q);
+          CHECK(q >= 1 && q <= TRD2_KS);
+          CHECK((long)(q - 1) * kc < m && m <= (long)q * kc);
+          CHECK(q == 1 || kc % 16 == 0);
+          CHECK(trd2_slice_count(m, q) == q);  // asking again for q slices gives the same split
+        }
+        CHECK(2L * kx * m * TRD2_SB <= trd2_kp_elems(n));
+        CHECK((long)ks * TRD2_SB * TRD2_SB <= trd2_kp_elems(n));
+      }
   if (failures) {
     std::printf("%d failures\n", failures);
     return 1;
