@@ -695,7 +695,8 @@ long panel_capacity() {
 // (device, stream).  A record's event is recorded on a stream of the library's own, made to wait
 // for the panel kernel first: a query of an event last recorded on a context's stream has failed
 // (hipErrorCapturedEvent) once that stream had been captured into its step-pair graphs, while the
-// library's stream is never captured.
+// library's stream is never captured.  Records, their events and the library's streams are kept
+// until the process ends (one per stream and device that ran a panel kernel).
 struct PanelSlot {
   hipEvent_t ev = nullptr;
   mfq_panel::Record rec;
