@@ -368,12 +368,15 @@ mfq_status mfq_set_pm_path(mfq_ctx *ctx, int32_t path);
  *                      otherwise grid-wide sweeps or panels of 32 reflectors that read the
  *                      trailing matrix once per reflector);
  *   MFQ_EIG_TWO_STAGE  dense -> band of half-width 32 by block reflectors whose two-sided
- *                      updates are matrix-core products, then band -> tridiagonal by bulge
- *                      chasing in a persistent kernel whose workgroups wait on each other
- *                      through progress words (a wait beyond 10 s makes the call return
- *                      MFQ_EDEVICE); used for orders >= 66 where the Rinv region holds its
- *                      storage (n^2 / 8 + 160 n complex entries per trajectory, at least about
- *                      16000), else one stage;
+ *                      updates are matrix-core products on the lower triangle (the column
+ *                      steps of a panel in one kernel whose workgroups wait on each other;
+ *                      such kernels of several streams are admitted only while they fit the
+ *                      GPU together), then band -> tridiagonal by bulge chasing in a
+ *                      persistent kernel whose workgroups wait on each other through progress
+ *                      words (any wait beyond 10 s makes the call return MFQ_EDEVICE); used
+ *                      for orders >= 66 where the Rinv region holds its storage (about
+ *                      n^2 / 8 + 160 n complex entries per trajectory for n >= 512, 19077 at
+ *                      n = 66), else one stage;
  *   MFQ_EIG_AUTO       two stages from order 4096 on, one below (default; measured on the
  *                      MI355X, two stages are faster from about that order). */
 #define MFQ_EIG_AUTO 0
